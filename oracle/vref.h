@@ -1,0 +1,104 @@
+/*
+ * vref.h -- plain CPU oracle for soft-decision Viterbi decoding of (beta,1,k)
+ * convolutional codes, full-frame and blocked-with-overlap.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the correctness reference that
+ * the GPU decoder is checked against.  Only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark may load it; the product decoder
+ * never calls it and shares no code, header, table or helper with it.
+ *
+ * Source: Mohammadidoost & Hashemi, "High-Throughput and Memory-Efficient
+ * Parallel Viterbi Decoder for Convolutional Codes on GPU" (arXiv 2011.09337).
+ *   encoder ............ Sec. II-A, eq. (1)
+ *   trellis / FSM ...... Sec. II-A (states are the k-1 previous inputs)
+ *   branch metric ...... Sec. II-B, eq. (2)
+ *   path metric, ACS ... Sec. II-B, eqs. (3)-(4), Algorithm 1 (forward)
+ *   traceback .......... Sec. II-B, Algorithm 2 (backward)
+ *   overlapping frames . Sec. III (frames of f bits, left overlap v1, right v2)
+ *
+ * Conventions (the paper leaves these open; each choice is listed in the design doc):
+ *   - gen[b] is a k-bit generator; its bit k-1 taps the current input in_t
+ *     and bit 0 taps in_{t-k+1} (eq. 1 multiplies in_t by g_{k-1}).
+ *   - output bit b of a stage is produced by gen[b], in the order listed.
+ *   - LLRs are time-major: llr[t*beta + b]; positive means "bit 0 likely".
+ *   - a state holds the k-1 previous inputs with the newest in the MSB.
+ *   - ACS ties go to the lower predecessor index; the final argmax picks the
+ *     lowest state index on ties.
+ *   - decoded bits are returned UNPACKED, one byte (0 or 1) per bit.
+ *
+ * Every function returns 0 on success and a negative value on invalid input.
+ */
+#ifndef VREF_H
+#define VREF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t k;        /* constraint length, 3..9            */
+  int32_t beta;     /* coded bits per input bit, 2..4     */
+  uint32_t gen[4];  /* generators, 0 < gen[b] < 2^k       */
+} vref_code;
+
+/* eq. (1): encode n bits; if terminated, k-1 zero tail inputs are appended.
+ * coded receives N*beta bytes (0/1), N = n + (terminated ? k-1 : 0). */
+int vref_encode(const vref_code *code, const uint8_t *bits, int64_t n,
+                int32_t terminated, uint8_t *coded);
+
+/* Full-frame maximum-likelihood decoding (Algorithms 1 and 2 over the whole
+ * stream).  llr holds N*beta values.  out receives n bytes.  If
+ * final_metric is not NULL it receives the path metric of the traced path. */
+int vref_decode_full_f32(const vref_code *code, const float *llr, int64_t n,
+                         int32_t terminated, uint8_t *out, float *final_metric);
+int vref_decode_full_f64(const vref_code *code, const double *llr, int64_t n,
+                         int32_t terminated, uint8_t *out, double *final_metric);
+/* Integer LLRs (e.g. int8-quantised), exact int64 path metrics. */
+int vref_decode_full_i8(const vref_code *code, const int8_t *llr, int64_t n,
+                        int32_t terminated, uint8_t *out, int64_t *final_metric);
+
+/* Blocked decoding with overlap (Sec. III): the n output bits are split into
+ * cores of L bits; block b covers trellis stages
+ *   [max(0, bL - v1), min(N, min((b+1)L, n) + v2))
+ * and emits only its core bits.  nthreads > 1 decodes blocks in parallel
+ * (OpenMP); results do not depend on nthreads. */
+int vref_decode_blocked_f32(const vref_code *code, const float *llr, int64_t n,
+                            int32_t terminated, int64_t L, int64_t v1, int64_t v2,
+                            uint8_t *out, int32_t nthreads);
+int vref_decode_blocked_f64(const vref_code *code, const double *llr, int64_t n,
+                            int32_t terminated, int64_t L, int64_t v1, int64_t v2,
+                            uint8_t *out, int32_t nthreads);
+int vref_decode_blocked_i8(const vref_code *code, const int8_t *llr, int64_t n,
+                           int32_t terminated, int64_t L, int64_t v1, int64_t v2,
+                           uint8_t *out, int32_t nthreads);
+
+/* One window of the blocked decoder, exposed for tests: run the forward
+ * procedure over stages [s, e) from either the known state 0 (start_known=1)
+ * or an unknown state (all path metrics 0), start the traceback from state 0
+ * (end_zero=1) or from the best state, and write bits for stages
+ * [emit_lo, emit_hi) to out[t - emit_lo]. */
+int vref_window_f64(const vref_code *code, const double *llr, int64_t s, int64_t e,
+                    int32_t start_known, int32_t end_zero, int64_t emit_lo,
+                    int64_t emit_hi, uint8_t *out, double *final_metric);
+
+/* Saturating int8 quantiser: q = clamp(round_half_even(llr * scale), -127, 127). */
+int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q);
+
+/* Exhaustive search over every input sequence of a window, for small windows
+ * only (prehistory + window inputs <= 24 bits).  The window covers stages
+ * [s, e) of an LLR stream; the k-1 inputs before stage s are free unless
+ * start_known (then 0); if end_zero the inputs of the last k-1 stages are 0.
+ * Among the sequences with the largest metric (eq. 2 summed over the window,
+ * in stage order, in double precision) it returns the one that is smallest
+ * when read as an integer whose most significant bit is the latest input.
+ * out receives the inputs of stages [s, e); best_metric the metric. */
+int vref_bruteforce_window(const vref_code *code, const double *llr, int64_t s,
+                           int64_t e, int32_t start_known, int32_t end_zero,
+                           uint8_t *out, double *best_metric);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,158 @@
+"""ctypes front end of the CPU oracle (oracle/libvref.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The GPU decoder never imports this module.
+
+All functions take and return numpy arrays.  Decoded bits come back unpacked,
+one uint8 (0 or 1) per bit.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvref.so")
+
+
+class VrefCode(C.Structure):
+    _fields_ = [("k", C.c_int32), ("beta", C.c_int32), ("gen", C.c_uint32 * 4)]
+
+
+try:
+    _lib = C.CDLL(LIB_PATH)
+except OSError:
+    _lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            import importlib.util
+            spec = importlib.util.spec_from_file_location("vref_build", os.path.join(HERE, "build.py"))
+            mod = importlib.util.module_from_spec(spec)
+            spec.loader.exec_module(mod)
+            mod.build()
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_P = C.c_void_p
+
+
+def _declare(L):
+    i64, i32 = C.c_int64, C.c_int32
+    L.vref_encode.argtypes = [C.POINTER(VrefCode), _P, i64, i32, _P]
+    for nm in ("vref_decode_full_f32", "vref_decode_full_f64", "vref_decode_full_i8"):
+        getattr(L, nm).argtypes = [C.POINTER(VrefCode), _P, i64, i32, _P, _P]
+    for nm in ("vref_decode_blocked_f32", "vref_decode_blocked_f64", "vref_decode_blocked_i8"):
+        getattr(L, nm).argtypes = [C.POINTER(VrefCode), _P, i64, i32, i64, i64, i64, _P, i32]
+    L.vref_window_f64.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, i64, i64, _P, _P]
+    L.vref_quantize_i8.argtypes = [_P, i64, C.c_float, _P]
+    L.vref_bruteforce_window.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, _P, _P]
+    for fn in (L.vref_encode, L.vref_decode_full_f32, L.vref_decode_full_f64, L.vref_decode_full_i8,
+               L.vref_decode_blocked_f32, L.vref_decode_blocked_f64, L.vref_decode_blocked_i8,
+               L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window):
+        fn.restype = C.c_int
+
+
+if _lib is not None:
+    _declare(_lib)
+
+
+def make_code(k, gens):
+    """Code (k, beta = len(gens), generators).  gens are ints (write octal as 0o171)."""
+    c = VrefCode()
+    c.k = int(k)
+    c.beta = len(gens)
+    for b, g in enumerate(gens):
+        c.gen[b] = int(g)
+    return c
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"{what} failed with status {rc}")
+
+
+def n_stages(code, n, terminated):
+    return int(n) + (code.k - 1 if terminated else 0)
+
+
+def encode(code, bits, terminated=True):
+    bits = np.ascontiguousarray(bits, dtype=np.uint8)
+    n = bits.size
+    out = np.zeros(n_stages(code, n, terminated) * code.beta, dtype=np.uint8)
+    _check(lib().vref_encode(C.byref(code), _ptr(bits), n, int(bool(terminated)), _ptr(out)), "vref_encode")
+    return out
+
+
+def decode_full(code, llr, n, terminated=True, want_metric=False):
+    """Full-frame ML decode.  dtype of llr selects the arithmetic: float32, float64, int8."""
+    llr = np.ascontiguousarray(llr)
+    assert llr.size == n_stages(code, n, terminated) * code.beta, "llr size"
+    out = np.zeros(n, dtype=np.uint8)
+    if llr.dtype == np.float32:
+        met = C.c_float()
+        fn = lib().vref_decode_full_f32
+    elif llr.dtype == np.float64:
+        met = C.c_double()
+        fn = lib().vref_decode_full_f64
+    elif llr.dtype == np.int8:
+        met = C.c_int64()
+        fn = lib().vref_decode_full_i8
+    else:
+        raise TypeError(llr.dtype)
+    _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), _ptr(out), C.byref(met)), fn.__name__)
+    return (out, met.value) if want_metric else out
+
+
+def split_overlap(v, v1=None):
+    """Default split of the overlap v into left v1 = floor(v/2) and right v2 = v - v1."""
+    if v1 is None or v1 < 0:
+        v1 = v // 2
+    return int(v1), int(v - v1)
+
+
+def decode_blocked(code, llr, n, L, v1, v2, terminated=True, nthreads=1):
+    """Blocked decode with overlap (left v1, right v2 stages) and cores of L bits."""
+    llr = np.ascontiguousarray(llr)
+    assert llr.size == n_stages(code, n, terminated) * code.beta, "llr size"
+    out = np.zeros(n, dtype=np.uint8)
+    fn = {np.dtype(np.float32): lib().vref_decode_blocked_f32,
+          np.dtype(np.float64): lib().vref_decode_blocked_f64,
+          np.dtype(np.int8): lib().vref_decode_blocked_i8}[llr.dtype]
+    _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), int(L), int(v1), int(v2), _ptr(out),
+              int(nthreads)), fn.__name__)
+    return out
+
+
+def window_f64(code, llr, s, e, start_known, end_zero, emit_lo, emit_hi):
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    out = np.zeros(max(emit_hi - emit_lo, 1), dtype=np.uint8)
+    met = C.c_double()
+    _check(lib().vref_window_f64(C.byref(code), _ptr(llr), s, e, int(start_known), int(end_zero),
+                                 emit_lo, emit_hi, _ptr(out), C.byref(met)), "vref_window_f64")
+    return out[: emit_hi - emit_lo], met.value
+
+
+def quantize_i8(llr, scale):
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    q = np.zeros(llr.size, dtype=np.int8)
+    _check(lib().vref_quantize_i8(_ptr(llr), llr.size, C.c_float(scale), _ptr(q)), "vref_quantize_i8")
+    return q
+
+
+def bruteforce_window(code, llr, s, e, start_known, end_zero):
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    out = np.zeros(e - s, dtype=np.uint8)
+    met = C.c_double()
+    _check(lib().vref_bruteforce_window(C.byref(code), _ptr(llr), s, e, int(start_known), int(end_zero),
+                                        _ptr(out), C.byref(met)), "vref_bruteforce_window")
+    return out, met.value
