@@ -1,0 +1,132 @@
+/*
+ * vit.h -- C ABI of the MI355X (gfx950) soft-decision Viterbi decoder.
+ *
+ * The library decodes a (beta,1,k) convolutional code from a stream of soft
+ * inputs (log-likelihood ratios), following Mohammadidoost & Hashemi,
+ * "High-Throughput and Memory-Efficient Parallel Viterbi Decoder for
+ * Convolutional Codes on GPU" (arXiv 2011.09337):
+ *   - branch metric: Sec. II-B, eq. (2);
+ *   - add-compare-select and survivor selection: Sec. II-B, eqs. (3)-(4),
+ *     forward procedure of Algorithm 1;
+ *   - traceback and decoding: Algorithm 2;
+ *   - overlapping frames (f = L decoded bits per block, left overlap v1,
+ *     right overlap v2): Sec. III; forward and backward in one kernel with
+ *     survivors kept on chip: Sec. IV-A.
+ *
+ * Conventions shared by every entry point:
+ *   - gen[b] is a k-bit generator; bit k-1 taps the current input in_t and
+ *     bit 0 taps in_{t-k+1} (eq. 1).  Output bit b of a stage is produced by
+ *     gen[b], b = 0..beta-1, and pairs with LLR slot b.
+ *   - LLRs are time-major and interleaved: llr[t*beta + b].  A positive LLR
+ *     means "coded bit 0 is more likely" (Sec. II-C).  For a terminated stream
+ *     the k-1 tail stages follow the n information stages, so the stream holds
+ *     N = n + k - 1 stages; an open stream holds N = n stages.
+ *   - Decoded bits are packed LSB first: bit t goes to byte t >> 3, bit
+ *     position t & 7.  out_bits must hold ceil(n/8) bytes; pad bits are 0.
+ *   - Ties: an add-compare-select tie keeps the lower predecessor index; the
+ *     traceback starts from the lowest-index state among those with the
+ *     largest path metric (VIT_TIE_LOWER_PRED, the only rule).
+ *   - Blocked geometry (Sec. III): block b decodes core bits
+ *     [bL, min((b+1)L, n)) from trellis stages
+ *     [max(0, bL - v1), min(N, min((b+1)L, n) + v2)).  A block that starts at
+ *     stage 0 starts from state 0; any other block starts with every path
+ *     metric 0.  A block that ends at stage N of a terminated stream traces
+ *     back from state 0; any other block from the best state.
+ *   - L = 0 selects full-frame decoding: one block holding every stage.
+ *
+ * Pointers to LLRs and to decoded bits are DEVICE memory owned by the caller;
+ * the library allocates no device memory on the decode path.
+ *
+ * Return values: VIT_OK (0) or a negative status.  Argument errors are found
+ * on the host before any device work (and need no GPU).  vit_last_error()
+ * returns a thread-local message describing the last failure.
+ */
+#ifndef VIT_H
+#define VIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VIT_ABI_VERSION 1
+
+enum {
+  VIT_OK = 0,
+  VIT_EINVAL = -1,        /* an argument is invalid                            */
+  VIT_EUNSUPPORTED = -2,  /* valid, but outside what the GPU kernel supports   */
+  VIT_ENOMEM = -3,        /* host allocation failed                            */
+  VIT_EDEVICE = -4,       /* a HIP runtime call or kernel launch failed        */
+  VIT_EBUSY = -5
+};
+
+enum { VIT_TIE_LOWER_PRED = 0 };
+enum { VIT_LLR_F32 = 0, VIT_LLR_I8 = 1 };
+
+/* A (beta,1,k) code: 3 <= k <= 9, 2 <= beta <= 4, 0 < gen[b] < 2^k. */
+typedef struct {
+  int32_t k;
+  int32_t beta;
+  uint32_t gen[4];
+} vit_code;
+
+/* Options of vit_decode_ex.  Fill with vit_opts_default() and set size. */
+typedef struct {
+  uint32_t size;         /* sizeof(vit_opts)                                     */
+  int32_t llr_type;      /* VIT_LLR_F32 (float) or VIT_LLR_I8 (int8, see below)  */
+  int32_t terminated;    /* 1: the stream carries k-1 tail stages (default 1)    */
+  int32_t v1;            /* left overlap; -1 = floor(v/2) (default -1)           */
+  int32_t check_finite;  /* reserved, must be 0                                  */
+  int32_t reserved;
+  void *stream;          /* hipStream_t to launch on; NULL = default stream      */
+} vit_opts;
+
+/* Decode n information bits from FP32 LLRs with blocks of L core bits and
+ * total overlap v (v1 = floor(v/2) on the left, v2 = v - v1 on the right), on
+ * a terminated stream.  L must be 0 (full frame) or a positive multiple of 8.
+ * Launches on the default stream and waits for completion.
+ * Errors: VIT_EINVAL for a bad code, NULL pointer, n <= 0, L < 0, v < 0 or an
+ * unknown tie rule; VIT_EUNSUPPORTED if L is not a multiple of 8 or one block's
+ * survivor storage exceeds the device's per-workgroup LDS; VIT_EDEVICE if a
+ * HIP call fails (including errors left by earlier work on the stream). */
+int vit_decode(const vit_code *code, const float *llr, int64_t n, int32_t L, int32_t v,
+               int32_t tie_rule, uint8_t *out_bits);
+
+/* As vit_decode, with options, asynchronous on opts->stream: returns once the
+ * work is queued; kernel faults surface at the caller's next synchronisation.
+ * With llr_type = VIT_LLR_I8 the LLRs are int8 values (any range, -128
+ * allowed) and the decoder computes exactly in integers: decisions are those
+ * of exact arithmetic on the int8 values.  opts may be NULL (defaults). */
+int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v,
+                  int32_t tie_rule, uint8_t *out_bits, const vit_opts *opts);
+
+/* Default options: FP32, terminated, v1 = floor(v/2), default stream. */
+vit_opts vit_opts_default(void);
+
+/* Geometry of a blocked decode, computed on the host (no device needed). */
+typedef struct {
+  int64_t n_stages;        /* N                                              */
+  int64_t n_blocks;        /* ceil(n / L)                                    */
+  int64_t v1, v2;          /* overlaps actually used                         */
+  int64_t stages_total;    /* sum over blocks of trellis stages processed    */
+  int64_t max_block_stages;
+  int64_t lds_bytes_per_block; /* survivor storage of one block (one wave)   */
+} vit_geometry;
+
+/* Fill *geo for the given decode arguments (same validation as vit_decode_ex,
+ * with v1 < 0 meaning floor(v/2)). */
+int vit_query_geometry(const vit_code *code, int64_t n, int32_t L, int32_t v, int32_t v1,
+                       int32_t terminated, vit_geometry *geo);
+
+/* Thread-local description of the last error ("" if none). */
+const char *vit_last_error(void);
+
+/* VIT_ABI_VERSION of the built library. */
+int vit_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

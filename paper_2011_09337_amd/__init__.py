@@ -1,0 +1,50 @@
+"""MI355X (gfx950) soft-decision Viterbi decoder for (beta,1,k) convolutional codes.
+
+Blocked decoding with overlap (Mohammadidoost & Hashemi, arXiv 2011.09337,
+Sec. III-IV): every step runs in HIP kernels behind the C ABI of
+include/vit.h.  This package only marshals torch device tensors into that ABI;
+PyTorch provides device memory and streams.
+"""
+from . import _lib
+from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_I8, VIT_OK,
+                   VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
+                   vit_last_error, vit_opts_default, vit_query_geometry)
+
+__all__ = ["decode", "make_code", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
+           "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
+           "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8",
+           "VIT_TIE_LOWER_PRED"]
+
+
+def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=None):
+    """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
+    values, time-major).  Returns (or fills) a uint8 device tensor of
+    ceil(n/8) packed bytes.  Asynchronous on `stream` (default: torch's
+    current stream)."""
+    import torch
+
+    if not llr.is_cuda or not llr.is_contiguous():
+        raise ValueError("llr must be a contiguous device tensor")
+    if llr.dtype == torch.float32:
+        llr_type = VIT_LLR_F32
+    elif llr.dtype == torch.int8:
+        llr_type = VIT_LLR_I8
+    else:
+        raise TypeError(f"llr dtype {llr.dtype} (float32 or int8 expected)")
+    nbytes = (int(n) + 7) // 8
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, device=llr.device)
+    elif out.numel() < nbytes or out.dtype != torch.uint8 or not out.is_cuda:
+        raise ValueError("out must be a uint8 device tensor of ceil(n/8) bytes")
+    N = int(n) + (code.k - 1 if terminated else 0)
+    if llr.numel() != N * code.beta:
+        raise ValueError(f"llr holds {llr.numel()} values, expected {N * code.beta}")
+    opts = vit_opts_default()
+    opts.llr_type = llr_type
+    opts.terminated = 1 if terminated else 0
+    opts.v1 = -1 if v1 is None else int(v1)
+    if stream is None:
+        stream = torch.cuda.current_stream(llr.device)
+    opts.stream = stream.cuda_stream
+    vit_decode_ex(code, llr.data_ptr(), int(n), int(L), int(v), VIT_TIE_LOWER_PRED, out.data_ptr(), opts)
+    return out

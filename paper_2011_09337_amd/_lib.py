@@ -1,0 +1,111 @@
+"""ctypes binding of libvit.so, the C ABI declared in include/vit.h.
+
+Argument marshalling only: every step of the decode runs in the HIP kernels.
+The functions keep the C names; `vit_decode` and `vit_decode_ex` take raw
+device addresses (ints) exactly like the C ABI.  If the library is missing
+this module raises on import: there is no fallback.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvit.so")
+
+VIT_OK = 0
+VIT_EINVAL = -1
+VIT_EUNSUPPORTED = -2
+VIT_ENOMEM = -3
+VIT_EDEVICE = -4
+VIT_EBUSY = -5
+VIT_TIE_LOWER_PRED = 0
+VIT_LLR_F32 = 0
+VIT_LLR_I8 = 1
+
+STATUS_NAMES = {VIT_OK: "VIT_OK", VIT_EINVAL: "VIT_EINVAL", VIT_EUNSUPPORTED: "VIT_EUNSUPPORTED",
+                VIT_ENOMEM: "VIT_ENOMEM", VIT_EDEVICE: "VIT_EDEVICE", VIT_EBUSY: "VIT_EBUSY"}
+
+
+class vit_code(C.Structure):
+    _fields_ = [("k", C.c_int32), ("beta", C.c_int32), ("gen", C.c_uint32 * 4)]
+
+
+class vit_opts(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("terminated", C.c_int32),
+                ("v1", C.c_int32), ("check_finite", C.c_int32), ("reserved", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class vit_geometry(C.Structure):
+    _fields_ = [("n_stages", C.c_int64), ("n_blocks", C.c_int64), ("v1", C.c_int64), ("v2", C.c_int64),
+                ("stages_total", C.c_int64), ("max_block_stages", C.c_int64),
+                ("lds_bytes_per_block", C.c_int64)]
+
+
+class VitError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc for gfx950)")
+
+lib = C.CDLL(LIB_PATH)
+
+_P = C.c_void_p
+lib.vit_decode.argtypes = [C.POINTER(vit_code), _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P]
+lib.vit_decode.restype = C.c_int
+lib.vit_decode_ex.argtypes = [C.POINTER(vit_code), _P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P,
+                              C.POINTER(vit_opts)]
+lib.vit_decode_ex.restype = C.c_int
+lib.vit_opts_default.argtypes = []
+lib.vit_opts_default.restype = vit_opts
+lib.vit_query_geometry.argtypes = [C.POINTER(vit_code), C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(vit_geometry)]
+lib.vit_query_geometry.restype = C.c_int
+lib.vit_last_error.argtypes = []
+lib.vit_last_error.restype = C.c_char_p
+lib.vit_abi_version.argtypes = []
+lib.vit_abi_version.restype = C.c_int
+
+
+def make_code(k, gens):
+    c = vit_code()
+    c.k = int(k)
+    c.beta = len(gens)
+    for b, g in enumerate(gens):
+        c.gen[b] = int(g)
+    return c
+
+
+def _check(status):
+    if status != VIT_OK:
+        raise VitError(status, vit_last_error())
+    return status
+
+
+def vit_last_error():
+    return lib.vit_last_error().decode()
+
+
+def vit_abi_version():
+    return lib.vit_abi_version()
+
+
+def vit_opts_default():
+    return lib.vit_opts_default()
+
+
+def vit_decode(code, llr_ptr, n, L, v, tie_rule, out_ptr):
+    return _check(lib.vit_decode(C.byref(code), llr_ptr, n, L, v, tie_rule, out_ptr))
+
+
+def vit_decode_ex(code, llr_ptr, n, L, v, tie_rule, out_ptr, opts=None):
+    return _check(lib.vit_decode_ex(C.byref(code), llr_ptr, n, L, v, tie_rule, out_ptr,
+                                    C.byref(opts) if opts is not None else None))
+
+
+def vit_query_geometry(code, n, L, v, v1=-1, terminated=1):
+    g = vit_geometry()
+    _check(lib.vit_query_geometry(C.byref(code), n, L, v, v1, terminated, C.byref(g)))
+    return g

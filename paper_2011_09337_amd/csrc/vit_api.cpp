@@ -1,0 +1,177 @@
+// vit_api.cpp -- the C ABI declared in include/vit.h: argument validation,
+// block geometry (Sec. III of the paper) and kernel launch.
+//
+// Validation happens entirely on the host before any HIP call, so argument
+// errors are reported without touching a device.
+#include "vit.h"
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "vit_internal.h"
+
+namespace {
+
+thread_local char t_err[512] = "";
+
+int fail(int status, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_err, sizeof(t_err), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+  return fail(VIT_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+int check_code(const vit_code *c) {
+  if (!c) return fail(VIT_EINVAL, "code is NULL");
+  if (c->k < 3 || c->k > 9) return fail(VIT_EINVAL, "k = %d outside [3, 9]", c->k);
+  if (c->beta < 2 || c->beta > 4) return fail(VIT_EINVAL, "beta = %d outside [2, 4]", c->beta);
+  for (int b = 0; b < c->beta; ++b) {
+    if (c->gen[b] == 0 || c->gen[b] >= (1u << c->k))
+      return fail(VIT_EINVAL, "generator %d = %u outside (0, 2^k)", b, c->gen[b]);
+  }
+  return VIT_OK;
+}
+
+struct Geometry {
+  int64_t N, L, v1, v2, nblocks, max_block_stages;
+};
+
+// Block b: core [bL, min((b+1)L, n)), stages [max(0, bL - v1), min(N, core_end + v2)).
+// L = 0 is the full frame: one block over all N stages.
+int resolve(const vit_code *code, int64_t n, int32_t L, int32_t v, int32_t v1_in, int32_t terminated,
+            Geometry *g) {
+  int st = check_code(code);
+  if (st) return st;
+  if (n <= 0) return fail(VIT_EINVAL, "n = %lld must be positive", (long long)n);
+  if (L < 0) return fail(VIT_EINVAL, "L = %d must be >= 0", L);
+  if (v < 0) return fail(VIT_EINVAL, "v = %d must be >= 0", v);
+  if (v1_in > v) return fail(VIT_EINVAL, "v1 = %d exceeds v = %d", v1_in, v);
+  if (terminated != 0 && terminated != 1) return fail(VIT_EINVAL, "terminated must be 0 or 1");
+  g->N = n + (terminated ? code->k - 1 : 0);
+  if (L == 0) {
+    g->L = n;
+    g->v1 = 0;
+    g->v2 = g->N - n;
+  } else {
+    g->L = L;
+    g->v1 = v1_in < 0 ? v / 2 : v1_in;
+    g->v2 = v - g->v1;
+  }
+  g->nblocks = (n + g->L - 1) / g->L;
+  // every block spans at most L + v1 + v2 stages (fewer where clipped to the stream)
+  const int64_t mx = g->L + g->v1 + g->v2 < g->N ? g->L + g->v1 + g->v2 : g->N;
+  g->max_block_stages = mx;
+  if (mx > (int64_t)1 << 30) return fail(VIT_EUNSUPPORTED, "block of %lld stages is too long", (long long)mx);
+  return VIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vit_last_error(void) { return t_err; }
+
+int vit_abi_version(void) { return VIT_ABI_VERSION; }
+
+vit_opts vit_opts_default(void) {
+  vit_opts o;
+  memset(&o, 0, sizeof(o));
+  o.size = sizeof(vit_opts);
+  o.llr_type = VIT_LLR_F32;
+  o.terminated = 1;
+  o.v1 = -1;
+  o.check_finite = 0;
+  o.stream = nullptr;
+  return o;
+}
+
+int vit_query_geometry(const vit_code *code, int64_t n, int32_t L, int32_t v, int32_t v1, int32_t terminated,
+                       vit_geometry *geo) {
+  t_err[0] = 0;
+  if (!geo) return fail(VIT_EINVAL, "geo is NULL");
+  Geometry g;
+  const int st = resolve(code, n, L, v, v1, terminated, &g);
+  if (st) return st;
+  geo->n_stages = g.N;
+  geo->n_blocks = g.nblocks;
+  geo->v1 = g.v1;
+  geo->v2 = g.v2;
+  int64_t total = 0;
+  for (int64_t b = 0; b < g.nblocks; ++b) {
+    const int64_t cs = b * g.L, ce = cs + g.L < n ? cs + g.L : n;
+    const int64_t s = cs - g.v1 > 0 ? cs - g.v1 : 0, e = ce + g.v2 < g.N ? ce + g.v2 : g.N;
+    total += e - s;
+  }
+  geo->stages_total = total;
+  geo->max_block_stages = g.max_block_stages;
+  geo->lds_bytes_per_block = vit::lds_bytes_per_block(code->k, code->beta, g.max_block_stages);
+  return VIT_OK;
+}
+
+int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v, int32_t tie_rule,
+                  uint8_t *out_bits, const vit_opts *opts) {
+  t_err[0] = 0;
+  vit_opts o = vit_opts_default();
+  if (opts) {
+    if (opts->size != sizeof(vit_opts)) return fail(VIT_EINVAL, "opts->size = %u, expected %zu", opts->size,
+                                                    sizeof(vit_opts));
+    o = *opts;
+  }
+  if (tie_rule != VIT_TIE_LOWER_PRED) return fail(VIT_EINVAL, "unknown tie rule %d", tie_rule);
+  if (!llr) return fail(VIT_EINVAL, "llr is NULL");
+  if (!out_bits) return fail(VIT_EINVAL, "out_bits is NULL");
+  if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8) return fail(VIT_EINVAL, "unknown llr_type %d",
+                                                                         o.llr_type);
+  if (o.check_finite != 0) return fail(VIT_EUNSUPPORTED, "check_finite is not implemented");
+  Geometry g;
+  int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
+  if (st) return st;
+  if (L > 0 && (L % 8) != 0) return fail(VIT_EUNSUPPORTED, "L = %d must be a multiple of 8", L);
+  if (o.llr_type == VIT_LLR_I8) {
+    // integer metrics are exact in fp32 while |metric| < 2^24
+    const int64_t bound = g.max_block_stages * 128 * code->beta;
+    if (bound >= ((int64_t)1 << 24))
+      return fail(VIT_EUNSUPPORTED, "int8 block of %lld stages may exceed exact fp32 integers",
+                  (long long)g.max_block_stages);
+  }
+  vit::DecodeArgs a;
+  a.llr = llr;
+  a.out = out_bits;
+  a.n = n;
+  a.N = g.N;
+  a.L = g.L;
+  a.v1 = g.v1;
+  a.v2 = g.v2;
+  a.nblocks = g.nblocks;
+  for (int b = 0; b < 4; ++b) a.gen[b] = b < code->beta ? code->gen[b] : 0;
+  a.k = code->k;
+  a.beta = code->beta;
+  a.terminated = o.terminated;
+  a.llr_type = o.llr_type;
+  a.max_block_stages = (int32_t)g.max_block_stages;
+  int unsupported = 0;
+  const char *why = "";
+  hipError_t e = vit::launch_blocked(a, (hipStream_t)o.stream, &unsupported, &why);
+  if (e != hipSuccess) return fail_hip(e, "launch");
+  if (unsupported) return fail(VIT_EUNSUPPORTED, "%s", why);
+  return VIT_OK;
+}
+
+int vit_decode(const vit_code *code, const float *llr, int64_t n, int32_t L, int32_t v, int32_t tie_rule,
+               uint8_t *out_bits) {
+  vit_opts o = vit_opts_default();
+  const int st = vit_decode_ex(code, llr, n, L, v, tie_rule, out_bits, &o);
+  if (st) return st;
+  const hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  return VIT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,619 @@
+// vit_decoder.h -- blocked soft-decision Viterbi decoder for gfx950 (MI355X):
+// device templates, instantiated per constraint length in vit_kernels_k*.hip.
+//
+// One wave decodes one block (a frame of L core bits with v1 stages of history
+// on the left and v2 on the right, Sec. III of the paper).  Forward procedure
+// (eqs. 2-4) and traceback (Algorithm 2) run in the same kernel, with the
+// survivor decisions kept in LDS for the block's lifetime (the point of the
+// paper's unified kernel, Sec. IV-A).  Design, mapped to CDNA4 rather than
+// following the paper's CUDA layout:
+//
+//  * State-per-slot layout.  Each of the S = 2^(k-1) states lives in one slot
+//    (lane, register): 64 lanes x S/64 registers, or one state per lane for
+//    k <= 7.  Instead of moving metrics to canonical positions each stage, the
+//    state held by a slot rotates: after m stages slot j holds state
+//    rotr^m(j) (k-1 bit rotation).  The two predecessors 2p, 2p+1 of a
+//    butterfly then always sit in slots that differ in one bit q = m mod (k-1),
+//    so each stage costs one pairwise exchange and no permutation.
+//  * Slot bits 0..5 map to lanes through the xor patterns 1, 2, 7, 8, 16, 32:
+//    the first four are single DPP patterns (quad_perm, row_half_mirror,
+//    row_ror:8) fused into the add; 16 and 32 go through ds_swizzle /
+//    ds_bpermute.  Slot bits 6.. are register bits (k = 8, 9).
+//  * Sign-folded ACS.  A slot whose own predecessor is odd keeps its path
+//    metric negated, so that "odd predecessor wins" is A > B in every lane and
+//    the survivor metric is max or min (v_med3 against +-inf).  Since the
+//    multiplier is +-1, fma(+-1, sigma, delta) rounds exactly like
+//    sigma +- delta: every metric equals the oracle's, bit for bit.
+//    Per state and stage: 2 fma, 1 compare, 1 med3, 1 add-with-carry that
+//    shifts the decision bit into a per-lane word.
+//  * Branch metrics (eq. 2): per tile of 64/2^beta stages the wave builds the
+//    2^beta branch metrics of each stage (one per lane, summed left to right);
+//    each stage every slot fetches its own one with ds_bpermute (LDS crossbar,
+//    no VALU).  The complement identity (eq. 8) gives the partner branch as a
+//    negation, folded into the fma.
+//  * Decisions: 32 stages per dword per lane, stored to LDS.  Traceback runs
+//    on the scalar unit: one v_readlane per stage; the lane to read moves by
+//    replacing one bit of the slot index with the decision bit.
+//  * The unrolled loop body covers lcm(k-1, tile, 32) stages; a block enters it
+//    at an offset (Duff's device) chosen so that its last stage is the body's
+//    last, which makes the final state of slot j equal to j.
+#pragma once
+
+#include "vit_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace vit {
+namespace dev {
+
+constexpr int largest_divisor_upto(int n, int cap) {
+  int best = 1;
+  for (int d = 1; d <= cap; ++d)
+    if (n % d == 0) best = d;
+  return best;
+}
+
+template <int K, int BETA>
+struct Shape {
+  static constexpr int P = K - 1;                      // bits of a state
+  static constexpr int S = 1 << P;                     // states
+  static constexpr int REGS = S > 64 ? S / 64 : 1;     // states per lane
+  static constexpr int NCODE = 1 << BETA;              // output patterns
+  // Unrolled body: a whole number of phase periods, at most 32 stages, so that
+  // one body's decision bits fill one dword per state slot.
+  static constexpr int BODY = P * (32 / P);
+  // Stages per branch-metric tile: a divisor of the body that fits 64 lanes.
+  static constexpr int T = largest_divisor_upto(BODY, 64 / NCODE);
+};
+
+// Physical lane xor pattern of slot bit q (q < 6).
+__host__ __device__ constexpr int lane_vec(int q) {
+  return q == 0 ? 1 : q == 1 ? 2 : q == 2 ? 7 : q == 3 ? 8 : q == 4 ? 16 : 32;
+}
+
+// Sign factor that register `reg` adds to the lane sign of phase q: bits q and
+// q-1 of the slot index (reg << 6 | lane slot) decide the sign convention.
+template <int P>
+__host__ __device__ constexpr bool reg_neg(int q, int reg) {
+  const int hi = reg << 6;
+  return (((hi >> q) ^ (hi >> ((q + P - 1) % P))) & 1) != 0;
+}
+
+__device__ __forceinline__ int parity32(uint32_t x) { return __builtin_popcount(x) & 1; }
+
+// ---------------------------------------------------------------- ACS kernels
+// o: this slot's stored metric (updated); x: branch metric of the partner
+// branch, sign-adjusted for this slot (consumed); d: decision word (shifted);
+// s: +-1 sign; c: +inf (keep max) or -inf (keep min).
+#define VIT_ACS_DPP_STD(DPPSTR, SN)                                              \
+  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], -%[x]\n\t"                     \
+               "s_nop 1\n\t"                                                     \
+               "v_fmac_f32_dpp %[x], %[o], " SN "%[s] " DPPSTR "\n\t"            \
+               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
+               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
+               "s_nop 0\n\t"                                                     \
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
+               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
+               : [s] "v"(s), [c] "v"(c)                                          \
+               : "vcc")
+
+#define VIT_ACS_DPP_GEN(DPPSTR, SN)                                              \
+  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], %[y]\n\t"                      \
+               "s_nop 1\n\t"                                                     \
+               "v_fmac_f32_dpp %[x], %[o], " SN "%[s] " DPPSTR "\n\t"            \
+               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
+               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
+               "s_nop 0\n\t"                                                     \
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
+               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
+               : [s] "v"(s), [c] "v"(c), [y] "v"(y)                              \
+               : "vcc")
+
+// Partner metric p already fetched (LDS crossbar exchange).
+#define VIT_ACS_P(SN, BTERM)                                                     \
+  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], " BTERM "\n\t"                 \
+               "v_fma_f32 %[x], " SN "%[s], %[p], %[x]\n\t"                      \
+               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
+               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
+               "s_nop 0\n\t"                                                     \
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
+               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
+               : [s] "v"(s), [c] "v"(c), [p] "v"(p), [y] "v"(y)                  \
+               : "vcc")
+
+// Both predecessors in the same lane (slot bit q >= 6 is a register bit):
+// registers a (own predecessor even) and b (odd).
+#define VIT_ACS_PAIR(SA, SB, BTA, BTB)                                           \
+  asm volatile("v_fma_f32 %[Ba], " SA "%[s], %[oa], " BTA "\n\t"                 \
+               "v_fma_f32 %[xa], " SA "%[s], %[ob], %[xa]\n\t"                   \
+               "v_fma_f32 %[Bb], " SB "%[s], %[ob], " BTB "\n\t"                 \
+               "v_fma_f32 %[xb], " SB "%[s], %[oa], %[xb]\n\t"                   \
+               "v_cmp_gt_f32 vcc, %[xa], %[Ba]\n\t"                              \
+               "v_med3_f32 %[oa], %[xa], %[Ba], %[ca]\n\t"                       \
+               "s_nop 0\n\t"                                                     \
+               "v_addc_co_u32 %[da], vcc, %[da], %[da], vcc\n\t"                 \
+               "v_cmp_gt_f32 vcc, %[xb], %[Bb]\n\t"                              \
+               "v_med3_f32 %[ob], %[xb], %[Bb], %[cb]\n\t"                       \
+               "s_nop 0\n\t"                                                     \
+               "v_addc_co_u32 %[db], vcc, %[db], %[db], vcc"                     \
+               : [oa] "+v"(oa), [ob] "+v"(ob), [xa] "+v"(xa), [xb] "+v"(xb),     \
+                 [da] "+v"(da), [db] "+v"(db), [Ba] "=&v"(Ba), [Bb] "=&v"(Bb)    \
+               : [s] "v"(s), [ca] "v"(ca), [cb] "v"(cb), [ya] "v"(ya), [yb] "v"(yb) \
+               : "vcc")
+
+#define VIT_DPP_Q0 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+#define VIT_DPP_Q1 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+#define VIT_DPP_Q2 "row_half_mirror row_mask:0xf bank_mask:0xf"
+#define VIT_DPP_Q3 "row_ror:8 row_mask:0xf bank_mask:0xf"
+
+template <int Q, bool NEG, bool STD>
+__device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, float s, float c, float y,
+                                         int xor32_addr) {
+  float B;
+  if constexpr (Q < 4) {
+#define VIT_DISPATCH_DPP(DPPSTR)                                        \
+  if constexpr (STD) {                                                  \
+    if constexpr (NEG) VIT_ACS_DPP_STD(DPPSTR, "-"); else VIT_ACS_DPP_STD(DPPSTR, ""); \
+  } else {                                                              \
+    if constexpr (NEG) VIT_ACS_DPP_GEN(DPPSTR, "-"); else VIT_ACS_DPP_GEN(DPPSTR, ""); \
+  }
+    if constexpr (Q == 0) { VIT_DISPATCH_DPP(VIT_DPP_Q0) }
+    else if constexpr (Q == 1) { VIT_DISPATCH_DPP(VIT_DPP_Q1) }
+    else if constexpr (Q == 2) { VIT_DISPATCH_DPP(VIT_DPP_Q2) }
+    else { VIT_DISPATCH_DPP(VIT_DPP_Q3) }
+#undef VIT_DISPATCH_DPP
+  } else {
+    float p;
+    const int ob = __builtin_bit_cast(int, o);
+    if constexpr (Q == 4) {
+      p = __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(ob, 0x401F));  // lane ^ 16
+    } else {
+      p = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(xor32_addr, ob));  // lane ^ 32
+    }
+    if constexpr (STD) {
+      if constexpr (NEG) VIT_ACS_P("-", "-%[x]"); else VIT_ACS_P("", "-%[x]");
+    } else {
+      if constexpr (NEG) VIT_ACS_P("-", "%[y]"); else VIT_ACS_P("", "%[y]");
+    }
+  }
+}
+
+template <bool NA, bool NB, bool STD>
+__device__ __forceinline__ void acs_pair(float &oa, float &ob, float &xa, float &xb, uint32_t &da,
+                                         uint32_t &db, float s, float ca, float cb, float ya, float yb) {
+  float Ba, Bb;
+#define VIT_PAIR_SIGNS(BTA, BTB)                                             \
+  if constexpr (NA && NB) VIT_ACS_PAIR("-", "-", BTA, BTB);                  \
+  else if constexpr (NA) VIT_ACS_PAIR("-", "", BTA, BTB);                    \
+  else if constexpr (NB) VIT_ACS_PAIR("", "-", BTA, BTB);                    \
+  else VIT_ACS_PAIR("", "", BTA, BTB);
+  if constexpr (STD) {
+    VIT_PAIR_SIGNS("-%[xa]", "-%[xb]")
+  } else {
+    VIT_PAIR_SIGNS("%[ya]", "%[yb]")
+  }
+#undef VIT_PAIR_SIGNS
+}
+
+// ---------------------------------------------------------------- decoder
+template <int K, int BETA, bool STD, bool I8>
+struct Decoder {
+  using Sh = Shape<K, BETA>;
+  static constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, NCODE = Sh::NCODE, T = Sh::T,
+                       BODY = Sh::BODY;
+  static constexpr int NY = STD ? 1 : P;
+  static constexpr int RY = STD ? 1 : REGS;
+
+  // per-lane constants (depend only on the code)
+  int addr_x[P][REGS];   // byte address of this slot's partner branch metric within a stage
+  int addr_y[NY][RY];    // own branch metric (codes without both end taps)
+  float sgn[P];          // sign convention product for register 0
+  float cmed[P];         // +inf / -inf for lane-bit phases
+  float bsign[BETA];     // signs of this lane's output pattern in the metric table
+  int tl;                // stage of this lane's metric table entry within a tile
+  int lane;
+  int slot0;             // slot index of register 0 in this lane
+  int xor32_addr;        // ds_bpermute byte address of lane ^ 32
+
+  // per-block state
+  float o[REGS];
+  uint32_t dec[REGS];
+  float xn[REGS], yn[REGS];  // branch metrics prefetched for the next step
+  int table;
+  int nxt[BETA];         // raw LLR words of the next tile (float bits or sign-extended int8)
+  const void *llr;
+  int64_t stage_base, s, e;
+  uint32_t *lds;
+  int body;
+
+  // Byte offset, within one stage of the metric table, of the branch metric a
+  // slot needs at phase q: the partner branch (own = false) or its own
+  // branch (own = true), negated (complemented pattern) if the slot keeps its
+  // metric negated.  Slot = (reg << 6) | slot0 holds state rotr^q(slot) as
+  // predecessor; the branch register is (input u << (k-1)) | predecessor with
+  // u = the predecessor's low bit, and the partner predecessor differs in bit 0.
+  __device__ __forceinline__ int metric_addr(const uint32_t *gen, int q, int reg, bool own) const {
+    const int st = ((reg << 6) | slot0) & (S - 1);
+    const int up = (st >> q) & 1;
+    const uint32_t iown = (uint32_t)(((st >> q) | (st << (P - q))) & (S - 1));
+    const uint32_t rown = ((uint32_t)up << (K - 1)) | iown;
+    const uint32_t rb = own ? rown : (rown ^ 1u);
+    int c = 0;
+#pragma unroll
+    for (int b = 0; b < BETA; ++b) c |= parity32(gen[b] & rb) << b;
+    return (c ^ (up ? NCODE - 1 : 0)) << 2;
+  }
+
+  __device__ __forceinline__ void setup(const uint32_t *gen) {
+    lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    slot0 = lane ^ (((lane >> 2) & 1) ? 3 : 0);  // inverse of the lane_vec map
+    xor32_addr = (lane ^ 32) << 2;
+    tl = lane >> BETA;
+    const int pat = lane & (NCODE - 1);
+#pragma unroll
+    for (int b = 0; b < BETA; ++b) bsign[b] = ((pat >> b) & 1) ? -1.0f : 1.0f;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) {
+        addr_x[q][reg] = metric_addr(gen, q, reg, false);
+        if constexpr (!STD) addr_y[q][reg] = metric_addr(gen, q, reg, true);
+      }
+      const int st0 = slot0 & (S - 1);
+      const int bq = (st0 >> q) & 1, bqm = (st0 >> ((q + P - 1) % P)) & 1;
+      sgn[q] = (bq ^ bqm) ? -1.0f : 1.0f;
+      cmed[q] = bq ? -INFINITY : INFINITY;
+    }
+  }
+
+  __device__ __forceinline__ void load_tile(int64_t tau) {
+    int64_t st = stage_base + tau * T + tl;
+    st = st < s ? s : (st >= e ? e - 1 : st);
+    if constexpr (I8) {
+      const int8_t *p = (const int8_t *)llr + st * BETA;
+#pragma unroll
+      for (int b = 0; b < BETA; ++b) nxt[b] = p[b];
+    } else {
+      const int *p = (const int *)llr + st * BETA;
+#pragma unroll
+      for (int b = 0; b < BETA; ++b) nxt[b] = p[b];
+    }
+  }
+
+  // eq. (2) for output pattern `pat` of this lane: sum in order b = 0..beta-1;
+  // fma with a +-1 multiplier rounds exactly like the plain add.
+  __device__ __forceinline__ float llr_value(int raw) const {
+    if constexpr (I8) return (float)raw;  // exact: |int8| <= 128
+    else return __builtin_bit_cast(float, raw);
+  }
+
+  __device__ __forceinline__ void build_table() {
+    float dl = llr_value(nxt[0]) * bsign[0];
+#pragma unroll
+    for (int b = 1; b < BETA; ++b) dl = __builtin_fmaf(bsign[b], llr_value(nxt[b]), dl);
+    table = __builtin_bit_cast(int, dl);
+  }
+
+  // Hide the per-lane branch-metric addresses from loop-invariant code motion
+  // so that each fetch keeps its tile offset in the instruction's offset field.
+  __device__ __forceinline__ void refresh_addresses() {
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) {
+        asm volatile("" : "+v"(addr_x[q][reg]));
+        if constexpr (!STD) asm volatile("" : "+v"(addr_y[q][reg]));
+      }
+  }
+
+  __device__ __forceinline__ float fetch(int addr, int tlc) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr + tlc * NCODE * 4, table));
+  }
+
+  // Branch metrics of the slots for the step at body offset G (tile table
+  // already holding G's tile).
+  template <int G>
+  __device__ __forceinline__ void fetch_step(float (&x)[REGS], float (&y)[REGS]) const {
+    constexpr int q = G % P;
+    constexpr int tlc = G % T;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      x[reg] = fetch(addr_x[q][reg], tlc);
+      if constexpr (!STD) y[reg] = fetch(addr_y[q][reg], tlc);
+      else y[reg] = 0.0f;
+    }
+  }
+
+  // Same, for a runtime body offset (the entry step of a block); the
+  // addresses are recomputed rather than indexed, to stay in registers.
+  __device__ __forceinline__ void fetch_entry(const uint32_t *gen, int g, float (&x)[REGS],
+                                              float (&y)[REGS]) const {
+    const int q = g % P, tlc = g % T;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      x[reg] = fetch(metric_addr(gen, q, reg, false), tlc);
+      y[reg] = STD ? 0.0f : fetch(metric_addr(gen, q, reg, true), tlc);
+    }
+  }
+
+  // One trellis stage at body offset G.  Software pipeline: the branch
+  // metrics of this step were fetched by the previous step (xn, yn); this
+  // step fetches the next step's before running its own ACS.  The LLRs of
+  // tile t+1 are loaded when tile t starts; its metric table is built at the
+  // last step of tile t.
+  template <int G>
+  __device__ __forceinline__ void step() {
+    constexpr int q = G % P;
+    constexpr int tlc = G % T;
+    float x[REGS], y[REGS];
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      x[reg] = xn[reg];
+      y[reg] = yn[reg];
+    }
+    if constexpr (tlc == 0) load_tile((int64_t)body * (BODY / T) + G / T + 1);
+    if constexpr (tlc == T - 1) build_table();
+    fetch_step<(G + 1) % BODY>(xn, yn);
+    if constexpr (q < 6) {
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) step_lane<q>(reg, x[reg], y[reg]);
+    } else {
+      constexpr int bit = 1 << (q - 6);
+#pragma unroll
+      for (int ra = 0; ra < REGS; ++ra) {
+        if ((ra & bit) == 0) step_pair<q>(ra, ra | bit, x[ra], x[ra | bit], y[ra], y[ra | bit]);
+      }
+    }
+    if constexpr (G == BODY - 1) {
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) lds[(body * REGS + reg) * 64 + lane] = dec[reg];
+    }
+  }
+
+  template <int Q>
+  __device__ __forceinline__ void step_lane(int reg, float x, float y) {
+    // unrolled by the caller, so `reg` is a constant after inlining
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) {
+      if (r == reg) {
+        if (reg_neg<P>(Q, r)) acs_lane<Q, true, STD>(o[r], x, dec[r], sgn[Q], cmed[Q], y, xor32_addr);
+        else acs_lane<Q, false, STD>(o[r], x, dec[r], sgn[Q], cmed[Q], y, xor32_addr);
+      }
+    }
+  }
+
+  template <int Q>
+  __device__ __forceinline__ void step_pair(int ra, int rb, float xa, float xb, float ya, float yb) {
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) {
+      if (r == ra) {
+        const bool na = reg_neg<P>(Q, ra), nb = reg_neg<P>(Q, rb);
+        const float cpos = INFINITY, cneg = -INFINITY;
+        if (na && nb) acs_pair<true, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
+        else if (na) acs_pair<true, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
+        else if (nb) acs_pair<false, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
+        else acs_pair<false, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
+      }
+    }
+  }
+};
+
+// The first (partial) body of a block: step G runs only from the entry offset
+// r on (uniform, scalar branches).  Later bodies run every step unguarded.
+#define VIT_G1(NN, M)                                        \
+  if constexpr ((NN) < (M)) {                                \
+    if ((NN) >= r) D.template step<(NN)>();                  \
+  }
+#define VIT_U1(NN, M)                                        \
+  if constexpr ((NN) < (M)) D.template step<(NN)>();
+#define VIT_X8(X, B, M)                                                                  \
+  X(B + 0, M) X(B + 1, M) X(B + 2, M) X(B + 3, M) X(B + 4, M) X(B + 5, M) X(B + 6, M)   \
+  X(B + 7, M)
+#define VIT_X32(X, M) VIT_X8(X, 0, M) VIT_X8(X, 8, M) VIT_X8(X, 16, M) VIT_X8(X, 24, M)
+
+template <int K, int BETA, bool STD, bool I8>
+__global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
+  using Dec = Decoder<K, BETA, STD, I8>;
+  using Sh = Shape<K, BETA>;
+  constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
+  static_assert(BODY <= 32, "unrolled body longer than one decision dword");
+  extern __shared__ uint32_t vit_lds[];
+
+  Dec D;
+  D.setup(a.gen);
+  // wave index and count are uniform across the wave: keep them scalar
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int wpb = (int)(blockDim.x >> 6);
+  D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
+  D.llr = a.llr;
+
+  // Blocks per wave, mapped so that neighbouring blocks (which share LLR
+  // overlap) run on the same XCD: workgroups are dealt round-robin to the 8
+  // XCDs, so XCD x gets a contiguous range of blocks.
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  int64_t first, stride, last;
+  if ((gridDim.x & 7) == 0 && a.nblocks >= nwaves) {
+    const int xcd = blockIdx.x & 7;
+    const int64_t wx = (int64_t)(blockIdx.x >> 3) * wpb + wid;
+    const int64_t per = (a.nblocks + 7) / 8;
+    first = (int64_t)xcd * per + wx;
+    last = (int64_t)(xcd + 1) * per;
+    if (last > a.nblocks) last = a.nblocks;
+    stride = nwaves / 8;
+  } else {
+    first = (int64_t)blockIdx.x * wpb + wid;
+    last = a.nblocks;
+    stride = nwaves;
+  }
+
+  for (int64_t blk = first; blk < last; blk += stride) {
+    const int64_t cs = blk * a.L;
+    const int64_t ce = (cs + a.L < a.n) ? cs + a.L : a.n;
+    const int64_t s = (cs - a.v1 > 0) ? cs - a.v1 : 0;
+    const int64_t e = (ce + a.v2 < a.N) ? ce + a.v2 : a.N;
+    const int M = (int)(e - s);
+    const int r = (BODY - M % BODY) % BODY;
+    const int nbody = (M + r) / BODY;
+    const bool start_known = (s == 0);
+    const bool end_zero = a.terminated && (e == a.N);
+    D.s = s;
+    D.e = e;
+    D.stage_base = s - r;
+    D.body = 0;
+
+    // Initial metrics: state 0 known at the stream start, else all zero.  The
+    // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
+    {
+      const int qm1 = (r + P - 1) % P;
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) {
+        const int slot = ((reg << 6) | D.slot0) & (S - 1);
+        const bool neg = (slot >> qm1) & 1;
+        D.o[reg] = (start_known && slot != 0) ? (neg ? INFINITY : -INFINITY) : 0.0f;
+        D.dec[reg] = 0u;
+      }
+    }
+    // Pipeline prologue for the entry step r: metric table of its tile, raw
+    // LLRs of the next tile (the step that starts a tile loads the next one),
+    // and the entry step's own branch metrics.
+    {
+      const int tau0 = r / T;
+      D.load_tile(tau0);
+      D.build_table();
+      if (r % T != 0) D.load_tile(tau0 + 1);
+      D.body = 0;
+      D.fetch_entry(a.gen, r, D.xn, D.yn);
+    }
+    D.body = 0;
+    D.refresh_addresses();
+    VIT_X32(VIT_G1, BODY)
+    for (D.body = 1; D.body < nbody; ++D.body) {
+      D.refresh_addresses();
+      VIT_X32(VIT_U1, BODY)
+    }
+
+    // ---- traceback start: after M + r (a multiple of BODY) steps, slot j holds state j.
+    constexpr int qlast = (BODY - 1) % P;
+    int lam = 0;
+    if (!end_zero) {
+      float best = -INFINITY;
+      int lab = 0x7fffffff;
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) {
+        const int slot = (reg << 6) | D.slot0;
+        const int label = slot & (S - 1);
+        const float sig = ((slot >> qlast) & 1) ? -D.o[reg] : D.o[reg];
+        if (reg == 0 || sig > best) {
+          best = sig;
+          lab = label;
+        }
+      }
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        const float ob = __shfl_xor(best, m);
+        const int ol = __shfl_xor(lab, m);
+        if (ob > best || (ob == best && ol < lab)) {
+          best = ob;
+          lab = ol;
+        }
+      }
+      lam = __builtin_amdgcn_readfirstlane(lab);
+    }
+
+    // ---- traceback (Algorithm 2), scalar: one decision bit per stage.
+    int lane_p = 0;
+#pragma unroll
+    for (int q = 0; q < 6 && q < P; ++q)
+      if ((lam >> q) & 1) lane_p ^= lane_vec(q);
+    int reg = lam >> 6;
+    int q = qlast;
+    int gcur = -1;
+    uint32_t dv[REGS];
+    uint32_t acc = 0;
+    int top = (int)(ce - s) - 1;  // highest local stage of the pending output word
+    const int mce = (int)(ce - s);
+    const int mstop = (int)(cs - s);
+    int grp = nbody - 1;
+    int pos = BODY - 1;  // g = grp * BODY + pos
+    for (int m = M - 1; m >= mstop; --m) {
+      if (grp != gcur) {
+#pragma unroll
+        for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
+        gcur = grp;
+      }
+      uint32_t w;
+      if constexpr (REGS == 1) {
+        w = __builtin_amdgcn_readlane(dv[0], lane_p);
+      } else {
+        w = __builtin_amdgcn_readlane(dv[0], lane_p);
+#pragma unroll
+        for (int rr = 1; rr < REGS; ++rr)
+          if (reg == rr) w = __builtin_amdgcn_readlane(dv[rr], lane_p);
+      }
+      const int d = (int)((w >> (BODY - 1 - pos)) & 1u);
+      const int u = (lam >> q) & 1;
+      if (m < mce) {
+        acc = (acc << 1) | (uint32_t)u;
+        const int64_t t = s + m;
+        if ((t & 31) == 0 || m == mstop) {
+          const int64_t b0 = t >> 3;
+          const int nb = (int)(((s + top) >> 3) - b0) + 1;
+          if (D.lane < nb) a.out[b0 + D.lane] = (uint8_t)(acc >> (8 * D.lane));
+          acc = 0;
+          top = m - 1;
+        }
+      }
+      if (u != d) {
+        lam ^= 1 << q;
+        if (q < 6) lane_p ^= lane_vec(q);
+        else reg ^= 1 << (q - 6);
+      }
+      q = (q == 0) ? P - 1 : q - 1;
+      if (pos == 0) {
+        pos = BODY - 1;
+        --grp;
+      } else {
+        --pos;
+      }
+    }
+  }
+}
+
+#undef VIT_G1
+#undef VIT_U1
+#undef VIT_X8
+#undef VIT_X32
+
+}  // namespace dev
+
+typedef void (*KernelFn)(DecodeArgs, int);
+
+// Kernel instance for (K, beta, standard code, int8 input).
+template <int K>
+KernelFn pick_kernel_k(int beta, bool stdc, bool i8) {
+  auto pick = [&](auto bt) -> KernelFn {
+    constexpr int B = decltype(bt)::value;
+    if (stdc) return i8 ? dev::vit_blocked_kernel<K, B, true, true> : dev::vit_blocked_kernel<K, B, true, false>;
+    return i8 ? dev::vit_blocked_kernel<K, B, false, true> : dev::vit_blocked_kernel<K, B, false, false>;
+  };
+  switch (beta) {
+    case 2: return pick(std::integral_constant<int, 2>{});
+    case 3: return pick(std::integral_constant<int, 3>{});
+    case 4: return pick(std::integral_constant<int, 4>{});
+  }
+  return nullptr;
+}
+
+KernelFn pick_kernel_k3(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k4(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k5(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k6(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k7(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k8(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k9(int beta, bool stdc, bool i8);
+
+}  // namespace vit

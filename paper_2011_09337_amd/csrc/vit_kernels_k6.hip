@@ -1,0 +1,6 @@
+// vit_kernels_k6.hip -- kernel instances for constraint length k = 6.
+#include "vit_decoder.h"
+
+namespace vit {
+KernelFn pick_kernel_k6(int beta, bool stdc, bool i8) { return pick_kernel_k<6>(beta, stdc, i8); }
+}  // namespace vit

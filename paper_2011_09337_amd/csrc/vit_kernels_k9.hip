@@ -1,0 +1,6 @@
+// vit_kernels_k9.hip -- kernel instances for constraint length k = 9.
+#include "vit_decoder.h"
+
+namespace vit {
+KernelFn pick_kernel_k9(int beta, bool stdc, bool i8) { return pick_kernel_k<9>(beta, stdc, i8); }
+}  // namespace vit

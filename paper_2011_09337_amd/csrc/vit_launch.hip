@@ -1,0 +1,95 @@
+// vit_launch.hip -- host side of the blocked decoder: kernel selection,
+// occupancy-based grid size, LDS sizing and launch.
+#include "vit_decoder.h"
+
+namespace vit {
+namespace {
+
+
+KernelFn pick_kernel(int k, int beta, bool stdc, bool i8) {
+  switch (k) {
+    case 3: return pick_kernel_k3(beta, stdc, i8);
+    case 4: return pick_kernel_k4(beta, stdc, i8);
+    case 5: return pick_kernel_k5(beta, stdc, i8);
+    case 6: return pick_kernel_k6(beta, stdc, i8);
+    case 7: return pick_kernel_k7(beta, stdc, i8);
+    case 8: return pick_kernel_k8(beta, stdc, i8);
+    case 9: return pick_kernel_k9(beta, stdc, i8);
+  }
+  return nullptr;
+}
+
+int body_len(int k) {
+  const int P = k - 1;
+  return P * (32 / P);
+}
+
+struct DeviceInfo {
+  int dev = -1;
+  int num_cu = 0;
+  int max_lds = 0;
+};
+thread_local DeviceInfo t_dev;
+
+}  // namespace
+
+int64_t lds_bytes_per_block(int k, int beta, int64_t max_block_stages) {
+  if (k < 3 || k > 9 || beta < 2 || beta > 4) return 0;
+  const int64_t body = body_len(k);
+  const int64_t regs = (k > 7) ? (1 << (k - 1)) / 64 : 1;
+  const int64_t bodies = (max_block_stages + body - 1) / body;  // block + entry offset fill whole bodies
+  return bodies * regs * 64 * 4;
+}
+
+hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsupported, const char **why) {
+  *unsupported = 0;
+  bool stdc = true;
+  for (int b = 0; b < a.beta; ++b) stdc = stdc && ((a.gen[b] >> (a.k - 1)) & 1u) && (a.gen[b] & 1u);
+  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type == 1);
+  if (!fn) {
+    *unsupported = 1;
+    *why = "no kernel instance for this (k, beta)";
+    return hipSuccess;
+  }
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if (t_dev.dev != dev) {
+    err = hipDeviceGetAttribute(&t_dev.num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    err = hipDeviceGetAttribute(&t_dev.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (err != hipSuccess) return err;
+    t_dev.dev = dev;
+  }
+  const int64_t lds_wave = lds_bytes_per_block(a.k, a.beta, a.max_block_stages);
+  if (lds_wave > t_dev.max_lds) {
+    *unsupported = 1;
+    *why = "one block's survivor storage exceeds the per-workgroup LDS";
+    return hipSuccess;
+  }
+  const int wpb = 1;
+  const size_t lds = (size_t)lds_wave * wpb;
+  int occ = 0;
+  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(fn), 64 * wpb, lds);
+  if (err != hipSuccess) return err;
+  if (occ < 1) occ = 1;
+  int64_t grid = (int64_t)occ * t_dev.num_cu;
+  const int64_t need = (a.nblocks + wpb - 1) / wpb;
+  if (grid >= need) grid = need;
+  else grid = grid / 8 * 8;
+  if (grid < 1) grid = 1;
+  if (lds > 65536) {
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  DecodeArgs args = a;
+  int words = (int)(lds_wave / 4);
+  void *kargs[] = {&args, &words};
+  err = hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3((unsigned)grid), dim3(64 * wpb), kargs, lds,
+                        stream);
+  if (err != hipSuccess) return err;
+  return hipGetLastError();
+}
+
+}  // namespace vit

@@ -1,0 +1,140 @@
+"""The C ABI on the host, without a GPU: the library loads, exports every
+function include/vit.h declares, validates arguments before any device work,
+and reports the block geometry of Sec. III."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def vit():
+    import paper_2011_09337_amd as v
+    return v
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "vit.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vit_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for want in ("vit_decode", "vit_decode_ex", "vit_query_geometry", "vit_last_error", "vit_abi_version",
+                 "vit_opts_default"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(vit):
+    for name in _declared_functions():
+        assert hasattr(vit._lib.lib, name), name
+
+
+def test_abi_version(vit):
+    assert vit.vit_abi_version() == 1
+
+
+def test_opts_default(vit):
+    o = vit.vit_opts_default()
+    assert o.size == 32 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
+    assert o.stream is None
+
+
+K7 = (7, (0o171, 0o133))
+
+
+def _code(vit, k=7, gens=(0o171, 0o133)):
+    return vit.make_code(k, gens)
+
+
+def _expect(vit, status, fn, *args):
+    with pytest.raises(vit.VitError) as ei:
+        fn(*args)
+    assert ei.value.status == status
+    assert vit.vit_last_error() != ""
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("k,gens", [(2, (3, 1)), (10, (0o1001, 0o1003)), (7, (0,  0o133)), (7, (0o200, 0o133)),
+                                    (7, (0o171,)), (7, (1, 2, 3, 4, 5))])
+def test_invalid_code(vit, k, gens):
+    c = vit.make_code(k, gens[:4]) if len(gens) <= 4 else vit.make_code(k, gens[:4])
+    if len(gens) > 4:
+        c.beta = 5
+    _expect(vit, vit.VIT_EINVAL, vit.vit_decode, c, FAKE, 100, 8, 4, 0, FAKE)
+
+
+def test_invalid_arguments(vit):
+    c = _code(vit)
+    E = vit.VIT_EINVAL
+    _expect(vit, E, vit.vit_decode, c, None, 100, 8, 4, 0, FAKE)       # NULL llr
+    _expect(vit, E, vit.vit_decode, c, FAKE, 100, 8, 4, 0, None)       # NULL out
+    _expect(vit, E, vit.vit_decode, c, FAKE, 0, 8, 4, 0, FAKE)         # n = 0
+    _expect(vit, E, vit.vit_decode, c, FAKE, -5, 8, 4, 0, FAKE)        # n < 0
+    _expect(vit, E, vit.vit_decode, c, FAKE, 100, -8, 4, 0, FAKE)      # L < 0
+    _expect(vit, E, vit.vit_decode, c, FAKE, 100, 8, -1, 0, FAKE)      # v < 0
+    _expect(vit, E, vit.vit_decode, c, FAKE, 100, 8, 4, 7, FAKE)       # unknown tie rule
+    o = vit.vit_opts_default()
+    o.v1 = 5
+    _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)  # v1 > v
+    o = vit.vit_opts_default()
+    o.llr_type = 9
+    _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+    o = vit.vit_opts_default()
+    o.size = 12
+    _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+    o = vit.vit_opts_default()
+    o.terminated = 2
+    _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+
+
+def test_unsupported_arguments(vit):
+    c = _code(vit)
+    U = vit.VIT_EUNSUPPORTED
+    _expect(vit, U, vit.vit_decode, c, FAKE, 100, 12, 4, 0, FAKE)      # L not a multiple of 8
+    o = vit.vit_opts_default()
+    o.check_finite = 1
+    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+    o = vit.vit_opts_default()
+    o.llr_type = vit.VIT_LLR_I8
+    # int8 metrics must stay exact in fp32: a block of 2^16 stages is refused
+    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
+
+
+def _blocks(n, N, L, v1, v2):
+    out = []
+    for cs in range(0, n, L):
+        ce = min(cs + L, n)
+        out.append((cs, ce, max(0, cs - v1), min(N, ce + v2)))
+    return out
+
+
+@pytest.mark.parametrize("n,L,v,v1,terminated", [(4096, 256, 42, -1, 1), (4096, 0, 42, -1, 1),
+                                                 (1 << 20, 128, 35, -1, 1), (1000, 8, 35, 30, 0),
+                                                 (7, 8, 3, -1, 1), (10, 64, 100, 99, 1)])
+def test_query_geometry_matches_definition(vit, n, L, v, v1, terminated):
+    k = 7
+    g = vit.vit_query_geometry(_code(vit), n, L, v, v1, terminated)
+    N = n + (k - 1 if terminated else 0)
+    if L == 0:
+        Le, e1, e2 = n, 0, N - n
+    else:
+        e1 = v // 2 if v1 < 0 else v1
+        Le, e2 = L, v - e1
+    blocks = _blocks(n, N, Le, e1, e2)
+    assert (g.n_stages, g.n_blocks, g.v1, g.v2) == (N, len(blocks), e1, e2)
+    assert g.stages_total == sum(e - s for (_, _, s, e) in blocks)
+    assert g.max_block_stages >= max(e - s for (_, _, s, e) in blocks)
+    assert g.max_block_stages == min(N, Le + e1 + e2)
+    assert g.lds_bytes_per_block > 0
+
+
+def test_config1_block_count_and_stages(vit):
+    # 4096 bits, L = 256, v = 42 -> v1 = v2 = 21: 16 blocks, 4732 stages in all
+    g = vit.vit_query_geometry(_code(vit), 4096, 256, 42, -1, 1)
+    assert (g.n_blocks, g.v1, g.v2, g.stages_total) == (16, 21, 21, 4732)

@@ -1,0 +1,216 @@
+"""GPU decoder (HIP, through the C ABI) against the CPU oracle, bit for bit.
+
+Every case runs the same seeded input through both and compares the packed
+decoded bits exactly: decisions are exact in both (fp32 sums rounded once in
+the same order, or exact integers for int8 LLRs), so any difference is a bug.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import vref
+
+pytestmark = pytest.mark.gpu
+
+CODES = {
+    "k7r12": (7, (0o171, 0o133)),
+    "k7r13": (7, (0o133, 0o171, 0o165)),
+    "k9r12": (9, (0o561, 0o753)),
+    "k3r12": (3, (0o7, 0o5)),
+    "k4r14": (4, (0o13, 0o15, 0o17, 0o11)),
+    "k5r12x": (5, (0o22, 0o35)),        # generator without the newest-input tap
+    "k6r12": (6, (0o53, 0o75)),
+    "k8r12": (8, (0o247, 0o371)),
+    "k5r13x": (5, (0o25, 0o33, 0o16)),  # generator without the oldest-input tap
+}
+NCPU = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_09337_amd as vit
+    return torch, vit
+
+
+def _gpu(dev, k, gens, llr, n, L, v, v1=None, terminated=True, stream=None):
+    torch, vit = dev
+    code = vit.make_code(k, gens)
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    print(f"[gpu] k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} term={terminated} "
+          f"dtype={llr.dtype}", flush=True)
+    out = vit.decode(code, t, n, L, v, v1=v1, terminated=terminated, stream=stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _oracle(k, gens, llr, n, L, v, v1=None, terminated=True):
+    code = vref.make_code(k, list(gens))
+    if L == 0:
+        bits = vref.decode_full(code, llr, n, terminated)
+    else:
+        e1 = v // 2 if v1 is None else v1
+        bits = vref.decode_blocked(code, llr, n, L, e1, v - e1, terminated, nthreads=NCPU)
+    return synth.pack_bits(bits)
+
+
+def _check(dev, k, gens, llr, n, L, v, v1=None, terminated=True):
+    got = _gpu(dev, k, gens, llr, n, L, v, v1, terminated)
+    want = _oracle(k, gens, llr, n, L, v, v1, terminated)
+    assert got.shape == want.shape
+    if not np.array_equal(got, want):
+        gb, wb = synth.unpack_bits(got, n), synth.unpack_bits(want, n)
+        bad = np.nonzero(gb != wb)[0]
+        raise AssertionError(f"{bad.size} of {n} bits differ; first at {bad[:8]}")
+
+
+def _awgn(k, gens, n, ebn0, seed, terminated=True):
+    rng = np.random.default_rng(seed)
+    bits = synth.info_bits(n, rng)
+    return synth.awgn_llr(synth.encode(k, gens, bits, terminated), ebn0, len(gens), rng)
+
+
+# ----------------------------------------------------------------------------- config 1
+
+def test_config1_full_and_blocked(dev):
+    # K=7 r1/2, n = 4096, Eb/N0 = 3 dB, seed 0; full frame and L = 256, v = 42
+    k, gens = CODES["k7r12"]
+    bits, llr = synth.make_stream("k7r12", 4096, 3.0, seed=0)
+    for L, v in ((0, 0), (256, 42)):
+        _check(dev, k, gens, llr, 4096, L, v)
+    got = synth.unpack_bits(_gpu(dev, k, gens, llr, 4096, 256, 42), 4096)
+    ml = vref.decode_full(vref.make_code(k, list(gens)), llr, 4096, True)
+    print(f"config1: BER blocked {np.mean(got != bits):.5f}, ML {np.mean(ml != bits):.5f}, "
+          f"blocked vs ML {np.mean(got != ml):.5f}")
+
+
+# ----------------------------------------------------------------------------- geometry sweep
+
+GEOMS = [
+    # n, L, v, v1, terminated
+    (1, 8, 0, None, True), (6, 8, 3, None, True), (7, 8, 1, None, False), (8, 8, 0, None, True),
+    (9, 8, 5, 0, True), (40, 8, 35, None, True), (40, 16, 0, None, False), (255, 32, 7, 3, True),
+    (256, 256, 42, None, True), (257, 256, 42, None, False), (1000, 0, 0, None, True),
+    (1000, 0, 0, None, False), (1001, 128, 35, 30, True), (3333, 64, 12, 12, False),
+    (6144, 256, 35, None, True), (6144, 1024, 45, None, True), (777, 8, 60, None, True),
+]
+
+
+@pytest.mark.parametrize("name", list(CODES))
+@pytest.mark.parametrize("n,L,v,v1,terminated", GEOMS)
+def test_geometry_sweep_awgn(dev, name, n, L, v, v1, terminated):
+    k, gens = CODES[name]
+    llr = _awgn(k, gens, n, 1.5, seed=n * 31 + L + v, terminated=terminated)
+    _check(dev, k, gens, llr, n, L, v, v1, terminated)
+
+
+# ----------------------------------------------------------------------------- ties and special values
+
+@pytest.mark.parametrize("name", list(CODES))
+def test_integer_llrs_with_ties(dev, name):
+    k, gens = CODES[name]
+    rng = np.random.default_rng(5)
+    for (n, L, v, terminated) in ((500, 16, 10, True), (500, 0, 0, False), (300, 8, 3, True)):
+        N = n + (k - 1 if terminated else 0)
+        llr = synth.integer_llr(N * len(gens), -2, 2, rng)
+        _check(dev, k, gens, llr, n, L, v, None, terminated)
+
+
+@pytest.mark.parametrize("name", ["k7r12", "k9r12", "k7r13", "k5r12x"])
+def test_all_zero_llrs(dev, name):
+    k, gens = CODES[name]
+    n = 700
+    llr = np.zeros((n + k - 1) * len(gens), dtype=np.float32)
+    _check(dev, k, gens, llr, n, 64, 20)
+    _check(dev, k, gens, llr, n, 0, 0)
+
+
+@pytest.mark.parametrize("name", ["k7r12", "k9r12", "k7r13"])
+def test_extreme_values(dev, name):
+    k, gens = CODES[name]
+    n = 600
+    N = n + k - 1
+    rng = np.random.default_rng(8)
+    base = _awgn(k, gens, n, 2.0, seed=3)
+    # huge magnitudes, denormals, signed zeros mixed in
+    for scale in (1e30, 1e-41, 1.0):
+        llr = (base * np.float32(scale)).astype(np.float32)
+        llr[rng.integers(0, llr.size, 50)] = -0.0
+        llr[rng.integers(0, llr.size, 50)] = 0.0
+        _check(dev, k, gens, llr, n, 32, 12)
+    assert N * len(gens) == base.size
+
+
+# ----------------------------------------------------------------------------- int8 LLRs
+
+@pytest.mark.parametrize("name", ["k7r12", "k7r13", "k9r12", "k4r14", "k5r12x"])
+def test_int8_llrs_exact(dev, name):
+    k, gens = CODES[name]
+    rng = np.random.default_rng(12)
+    for (n, L, v) in ((2000, 128, 35), (600, 0, 0), (999, 8, 45)):
+        N = n + k - 1
+        q = rng.integers(-128, 128, size=N * len(gens)).astype(np.int8)
+        _check(dev, k, gens, q, n, L, v)
+        qs = vref.quantize_i8(_awgn(k, gens, n, 2.0, seed=n), 8.0)
+        _check(dev, k, gens, qs, n, L, v)
+
+
+# ----------------------------------------------------------------------------- many blocks
+
+@pytest.mark.parametrize("L", [128, 256, 512, 1024])
+def test_many_blocks_k7(dev, L):
+    # 2^21 bits: more blocks than resident waves, so each wave loops over
+    # blocks and the XCD-contiguous block mapping is exercised.
+    k, gens = CODES["k7r12"]
+    n = 1 << 21
+    llr = _awgn(k, gens, n, 2.0, seed=L)
+    _check(dev, k, gens, llr, n, L, 35)
+
+
+def test_many_blocks_k9_and_r13(dev):
+    for name, n, L, v in (("k9r12", 1 << 18, 256, 45), ("k7r13", 1 << 19, 256, 35)):
+        k, gens = CODES[name]
+        _check(dev, k, gens, _awgn(k, gens, n, 2.0, seed=9), n, L, v)
+
+
+# ----------------------------------------------------------------------------- streams and determinism
+
+def test_nondefault_stream_and_repeatability(dev):
+    torch, vit = dev
+    k, gens = CODES["k7r12"]
+    n = 50000
+    llr = _awgn(k, gens, n, 1.0, seed=77)
+    s = torch.cuda.Stream()
+    a = _gpu(dev, k, gens, llr, n, 256, 35, stream=s)
+    b = _gpu(dev, k, gens, llr, n, 256, 35)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, _oracle(k, gens, llr, n, 256, 35))
+
+
+def test_synchronous_entry_point(dev):
+    torch, vit = dev
+    k, gens = CODES["k7r12"]
+    n = 3000
+    llr = _awgn(k, gens, n, 3.0, seed=1)
+    t = torch.from_numpy(llr).cuda()
+    out = torch.zeros((n + 7) // 8, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    vit.vit_decode(vit.make_code(k, gens), t.data_ptr(), n, 256, 42, 0, out.data_ptr())
+    np.testing.assert_array_equal(out.cpu().numpy(), _oracle(k, gens, llr, n, 256, 42))
+
+
+# ----------------------------------------------------------------------------- full size
+
+@pytest.mark.parametrize("L", [128, 1024])
+def test_full_size_stream_k7(dev, L):
+    # the 2^24-bit stream of the throughput workload, in the benchmark's launch
+    # configuration; the oracle decodes it completely (all host cores)
+    k, gens = CODES["k7r12"]
+    n = 1 << 24
+    bits, llr = synth.make_stream("k7r12", n, 3.0, seed=1 + 3)
+    _check(dev, k, gens, llr, n, L, 35)
