@@ -227,6 +227,8 @@ struct Decoder {
   int nxt[BETA];         // raw LLR words of the next tile (float bits or sign-extended int8)
   const void *llr;
   int64_t stage_base, s, e;
+  int tile_stage0;       // stage_base + this lane's table row
+  int s_lo, s_hi;        // first and last stage of the block
   uint32_t *lds;
   int body;
 
@@ -270,15 +272,20 @@ struct Decoder {
     }
   }
 
-  __device__ __forceinline__ void load_tile(int64_t tau) {
-    int64_t st = stage_base + tau * T + tl;
-    st = st < s ? s : (st >= e ? e - 1 : st);
+  // LLRs of tile tau (stages stage_base + tau*T + 0..T-1, one per table row),
+  // clamped into the block so every lane reads inside the stream.  Offsets are
+  // 32-bit (the host guarantees N*beta*sizeof(LLR) < 2^32).
+  __device__ __forceinline__ void load_tile(int tau) {
+    const int raw = tile_stage0 + tau * T;
+    const int stc = __builtin_elementwise_max(__builtin_elementwise_min(raw, s_hi), s_lo);
+    const uint32_t off = (uint32_t)stc * (uint32_t)(BETA * (I8 ? 1 : 4));
+    const char *base = (const char *)llr;
     if constexpr (I8) {
-      const int8_t *p = (const int8_t *)llr + st * BETA;
+      const int8_t *p = (const int8_t *)(base + off);
 #pragma unroll
       for (int b = 0; b < BETA; ++b) nxt[b] = p[b];
     } else {
-      const int *p = (const int *)llr + st * BETA;
+      const int *p = (const int *)(base + off);
 #pragma unroll
       for (int b = 0; b < BETA; ++b) nxt[b] = p[b];
     }
@@ -355,7 +362,7 @@ struct Decoder {
       x[reg] = xn[reg];
       y[reg] = yn[reg];
     }
-    if constexpr (tlc == 0) load_tile((int64_t)body * (BODY / T) + G / T + 1);
+    if constexpr (tlc == 0) load_tile(body * (BODY / T) + G / T + 1);
     if constexpr (tlc == T - 1) build_table();
     fetch_step<(G + 1) % BODY>(xn, yn);
     if constexpr (q < 6) {
@@ -370,7 +377,7 @@ struct Decoder {
     }
     if constexpr (G == BODY - 1) {
 #pragma unroll
-      for (int reg = 0; reg < REGS; ++reg) lds[(body * REGS + reg) * 64 + lane] = dec[reg];
+      for (int reg = 0; reg < REGS; ++reg) lds[(body * REGS + reg) * 64 + slot0] = dec[reg];
     }
   }
 
@@ -463,6 +470,9 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
     D.s = s;
     D.e = e;
     D.stage_base = s - r;
+    D.tile_stage0 = (int)(s - r) + D.tl;
+    D.s_lo = (int)s;
+    D.s_hi = (int)e - 1;
     D.body = 0;
 
     // Initial metrics: state 0 known at the stream start, else all zero.  The
@@ -524,60 +534,53 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
       lam = __builtin_amdgcn_readfirstlane(lab);
     }
 
-    // ---- traceback (Algorithm 2), scalar: one decision bit per stage.
-    int lane_p = 0;
+    // ---- traceback (Algorithm 2) on the scalar unit.  lam is the slot index
+    // of the current state; the decision words are stored by slot, so its
+    // decision bit is bit (BODY-1-pos) of lane lam & 63 of register lam >> 6.
+    // Following the survivor replaces bit q = (body offset) mod (k-1) of the
+    // slot index with that decision bit.  The decision bit read at body offset
+    // g is the input bit of offset g - (k-1) (the oldest input of the state),
+    // so the decision stream, followed by the k-1 bits of the start slot, is
+    // the decoded sequence shifted by k-1: bit t of the output is stream bit
+    // (t - stage_base) + k - 1.  Each group's 32-bit stream word replaces the
+    // first decision dword of its group in LDS.
+    const uint32_t lam_start = (uint32_t)lam;
+    const int grp_lo = ((int)(cs - s) + r) / BODY;
+    for (int grp = nbody - 1; grp >= grp_lo; --grp) {
+      uint32_t dv[REGS];
 #pragma unroll
-    for (int q = 0; q < 6 && q < P; ++q)
-      if ((lam >> q) & 1) lane_p ^= lane_vec(q);
-    int reg = lam >> 6;
-    int q = qlast;
-    int gcur = -1;
-    uint32_t dv[REGS];
-    uint32_t acc = 0;
-    int top = (int)(ce - s) - 1;  // highest local stage of the pending output word
-    const int mce = (int)(ce - s);
-    const int mstop = (int)(cs - s);
-    int grp = nbody - 1;
-    int pos = BODY - 1;  // g = grp * BODY + pos
-    for (int m = M - 1; m >= mstop; --m) {
-      if (grp != gcur) {
+      for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
+      uint32_t acc = 0;
 #pragma unroll
-        for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
-        gcur = grp;
-      }
-      uint32_t w;
-      if constexpr (REGS == 1) {
-        w = __builtin_amdgcn_readlane(dv[0], lane_p);
-      } else {
-        w = __builtin_amdgcn_readlane(dv[0], lane_p);
+      for (int pos = BODY - 1; pos >= 0; --pos) {
+        const int q = pos % P;
+        uint32_t w = __builtin_amdgcn_readlane(dv[0], lam & 63);
 #pragma unroll
         for (int rr = 1; rr < REGS; ++rr)
-          if (reg == rr) w = __builtin_amdgcn_readlane(dv[rr], lane_p);
+          if ((lam >> 6) == rr) w = __builtin_amdgcn_readlane(dv[rr], lam & 63);
+        const uint32_t d = (w >> (BODY - 1 - pos)) & 1u;
+        acc = (acc << 1) | d;
+        lam = (int)(((uint32_t)lam & ~(1u << q)) | (d << q));
       }
-      const int d = (int)((w >> (BODY - 1 - pos)) & 1u);
-      const int u = (lam >> q) & 1;
-      if (m < mce) {
-        acc = (acc << 1) | (uint32_t)u;
-        const int64_t t = s + m;
-        if ((t & 31) == 0 || m == mstop) {
-          const int64_t b0 = t >> 3;
-          const int nb = (int)(((s + top) >> 3) - b0) + 1;
-          if (D.lane < nb) a.out[b0 + D.lane] = (uint8_t)(acc >> (8 * D.lane));
-          acc = 0;
-          top = m - 1;
-        }
-      }
-      if (u != d) {
-        lam ^= 1 << q;
-        if (q < 6) lane_p ^= lane_vec(q);
-        else reg ^= 1 << (q - 6);
-      }
-      q = (q == 0) ? P - 1 : q - 1;
-      if (pos == 0) {
-        pos = BODY - 1;
-        --grp;
-      } else {
-        --pos;
+      D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
+    }
+
+    // ---- output: lane-parallel assembly of the core bits [cs, ce) into bytes.
+    {
+      const int64_t b_lo = cs >> 3, b_hi = (ce - 1) >> 3;
+      const uint32_t body_mask = BODY == 32 ? 0xffffffffu : ((1u << BODY) - 1u);
+      for (int64_t B = b_lo + D.lane; B <= b_hi; B += 64) {
+        const int gbit = (int)(8 * B - D.stage_base) + P;  // stream index of the byte's bit 0
+        const int wa_i = gbit / BODY, sh = gbit - wa_i * BODY;
+        auto word = [&](int i) -> uint64_t {
+          if (i < nbody) return D.lds[(i * REGS) * 64] & body_mask;
+          return i == nbody ? lam_start : 0u;
+        };
+        const uint64_t cat = word(wa_i) | (word(wa_i + 1) << BODY);
+        uint32_t byte = (uint32_t)(cat >> sh) & 0xffu;
+        const int64_t nvalid = ce - 8 * B;
+        if (nvalid < 8) byte &= (1u << nvalid) - 1u;
+        a.out[B] = (uint8_t)byte;
       }
     }
   }
