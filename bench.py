@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -132,6 +134,13 @@ def main():
         if L == args.L:
             head_wall = wall
     head = sweep[args.L]
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # decode once more for the BER of the headline configuration
     vit.decode(code, llr_d, n, args.L, v, out=out_d)
     torch.cuda.synchronize()

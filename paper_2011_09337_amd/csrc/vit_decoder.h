@@ -17,8 +17,8 @@
 //    so each stage costs one pairwise exchange and no permutation.
 //  * Slot bits 0..5 map to lanes through the xor patterns 1, 2, 7, 8, 16, 32:
 //    the first four are single DPP patterns (quad_perm, row_half_mirror,
-//    row_ror:8) fused into the add; 16 and 32 go through ds_swizzle /
-//    ds_bpermute.  Slot bits 6.. are register bits (k = 8, 9).
+//    row_ror:8) fused into the add; 16 and 32 are in-place v_permlane16_swap /
+//    v_permlane32_swap.  Slot bits 6.. are register bits (k = 8, 9).
 //  * Sign-folded ACS.  A slot whose own predecessor is odd keeps its path
 //    metric negated, so that "odd predecessor wins" is A > B in every lane and
 //    the survivor metric is max or min (v_med3 against +-inf).  Since the
@@ -86,64 +86,69 @@ __host__ __device__ constexpr bool reg_neg(int q, int reg) {
 __device__ __forceinline__ int parity32(uint32_t x) { return __builtin_popcount(x) & 1; }
 
 // ---------------------------------------------------------------- ACS kernels
-// o: this slot's stored metric (updated); x: branch metric of the partner
-// branch, sign-adjusted for this slot (consumed); d: decision word (shifted);
-// s: +-1 sign; c: +inf (keep max) or -inf (keep min).
-#define VIT_ACS_DPP_STD(DPPSTR, SN)                                              \
-  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], -%[x]\n\t"                     \
-               "s_nop 1\n\t"                                                     \
-               "v_fmac_f32_dpp %[x], %[o], " SN "%[s] " DPPSTR "\n\t"            \
-               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
-               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
-               "s_nop 0\n\t"                                                     \
-               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
-               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
-               : [s] "v"(s), [c] "v"(c)                                          \
+// One ACS of one slot: o is the slot's stored metric (updated), x the
+// partner branch metric, sign-adjusted for this slot (consumed), s = +-1,
+// c = +inf (keep the max) or -inf (keep the min).  The compare mask of this
+// stage is returned in `pend` and shifted into the decision word d by the NEXT
+// stage's block (d = 2d + pend), which keeps every hazard distance >= 2
+// instructions without s_nop:
+//   * the DPP read of o comes 2 VALU ops after the previous stage's med3 wrote it;
+//   * the VALU-written compare mask is read as a carry 2 VALU ops after.
+// Instruction order: B = s*o - x; d += prev mask; A = s*o(partner) + x;
+// mask = A > B; o = med3(A, B, c).
+#define VIT_ACS_DPP(DPPSTR, SN, BTERM)                                                   \
+  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], " BTERM "\n\t"                         \
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], %[pd]\n\t"                          \
+               "v_fmac_f32_dpp %[x], %[o], " SN "%[s] " DPPSTR "\n\t"                    \
+               "v_cmp_gt_f32 %[pd], %[x], %[B]\n\t"                                      \
+               "v_med3_f32 %[o], %[x], %[B], %[c]"                                       \
+               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B), [pd] "+s"(pend)    \
+               : [s] "v"(s), [c] "v"(c), [y] "v"(y)                                      \
                : "vcc")
 
-#define VIT_ACS_DPP_GEN(DPPSTR, SN)                                              \
-  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], %[y]\n\t"                      \
-               "s_nop 1\n\t"                                                     \
-               "v_fmac_f32_dpp %[x], %[o], " SN "%[s] " DPPSTR "\n\t"            \
-               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
-               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
-               "s_nop 0\n\t"                                                     \
-               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
-               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
-               : [s] "v"(s), [c] "v"(c), [y] "v"(y)                              \
-               : "vcc")
-
-// Partner metric p already fetched (LDS crossbar exchange).
-#define VIT_ACS_P(SN, BTERM)                                                     \
-  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], " BTERM "\n\t"                 \
-               "v_fma_f32 %[x], " SN "%[s], %[p], %[x]\n\t"                      \
-               "v_cmp_gt_f32 vcc, %[x], %[B]\n\t"                                \
-               "v_med3_f32 %[o], %[x], %[B], %[c]\n\t"                           \
-               "s_nop 0\n\t"                                                     \
-               "v_addc_co_u32 %[d], vcc, %[d], %[d], vcc"                        \
-               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B)             \
-               : [s] "v"(s), [c] "v"(c), [p] "v"(p), [y] "v"(y)                  \
+// Slot bits 4 and 5 flip lane bits 4 and 5 (xor 16 / xor 32): the partner
+// metric comes from v_permlane16_swap / v_permlane32_swap of o with itself,
+// which exchanges the two halves of each row pair / of the wave in place (o is
+// dead after B, and rewritten by med3).  Same hazard distances as the DPP form.
+#define VIT_ACS_PERM(PERM, SN, BTERM)                                                    \
+  asm volatile("v_fma_f32 %[B], " SN "%[s], %[o], " BTERM "\n\t"                         \
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], %[pd]\n\t"                          \
+               PERM " %[o], %[o]\n\t"                                                    \
+               "v_fma_f32 %[x], " SN "%[s], %[o], %[x]\n\t"                              \
+               "v_cmp_gt_f32 %[pd], %[x], %[B]\n\t"                                      \
+               "v_med3_f32 %[o], %[x], %[B], %[c]"                                       \
+               : [o] "+v"(o), [x] "+v"(x), [d] "+v"(d), [B] "=&v"(B), [pd] "+s"(pend)    \
+               : [s] "v"(s), [c] "v"(c), [y] "v"(y)                                      \
                : "vcc")
 
 // Both predecessors in the same lane (slot bit q >= 6 is a register bit):
 // registers a (own predecessor even) and b (odd).
-#define VIT_ACS_PAIR(SA, SB, BTA, BTB)                                           \
-  asm volatile("v_fma_f32 %[Ba], " SA "%[s], %[oa], " BTA "\n\t"                 \
-               "v_fma_f32 %[xa], " SA "%[s], %[ob], %[xa]\n\t"                   \
-               "v_fma_f32 %[Bb], " SB "%[s], %[ob], " BTB "\n\t"                 \
-               "v_fma_f32 %[xb], " SB "%[s], %[oa], %[xb]\n\t"                   \
-               "v_cmp_gt_f32 vcc, %[xa], %[Ba]\n\t"                              \
-               "v_med3_f32 %[oa], %[xa], %[Ba], %[ca]\n\t"                       \
-               "s_nop 0\n\t"                                                     \
-               "v_addc_co_u32 %[da], vcc, %[da], %[da], vcc\n\t"                 \
-               "v_cmp_gt_f32 vcc, %[xb], %[Bb]\n\t"                              \
-               "v_med3_f32 %[ob], %[xb], %[Bb], %[cb]\n\t"                       \
-               "s_nop 0\n\t"                                                     \
-               "v_addc_co_u32 %[db], vcc, %[db], %[db], vcc"                     \
-               : [oa] "+v"(oa), [ob] "+v"(ob), [xa] "+v"(xa), [xb] "+v"(xb),     \
-                 [da] "+v"(da), [db] "+v"(db), [Ba] "=&v"(Ba), [Bb] "=&v"(Bb)    \
-               : [s] "v"(s), [ca] "v"(ca), [cb] "v"(cb), [ya] "v"(ya), [yb] "v"(yb) \
+#define VIT_ACS_PAIR(SA, SB, BTA, BTB)                                                   \
+  asm volatile("v_fma_f32 %[Ba], " SA "%[s], %[oa], " BTA "\n\t"                         \
+               "v_addc_co_u32 %[da], vcc, %[da], %[da], %[pa]\n\t"                       \
+               "v_fma_f32 %[xa], " SA "%[s], %[ob], %[xa]\n\t"                           \
+               "v_fma_f32 %[Bb], " SB "%[s], %[ob], " BTB "\n\t"                         \
+               "v_addc_co_u32 %[db], vcc, %[db], %[db], %[pb]\n\t"                       \
+               "v_fma_f32 %[xb], " SB "%[s], %[oa], %[xb]\n\t"                           \
+               "v_cmp_gt_f32 %[pa], %[xa], %[Ba]\n\t"                                    \
+               "v_med3_f32 %[oa], %[xa], %[Ba], %[ca]\n\t"                               \
+               "v_cmp_gt_f32 %[pb], %[xb], %[Bb]\n\t"                                    \
+               "v_med3_f32 %[ob], %[xb], %[Bb], %[cb]"                                   \
+               : [oa] "+v"(oa), [ob] "+v"(ob), [xa] "+v"(xa), [xb] "+v"(xb),             \
+                 [da] "+v"(da), [db] "+v"(db), [Ba] "=&v"(Ba), [Bb] "=&v"(Bb),           \
+                 [pa] "+s"(pa), [pb] "+s"(pb)                                            \
+               : [s] "v"(s), [ca] "v"(ca), [cb] "v"(cb), [ya] "v"(ya), [yb] "v"(yb)      \
                : "vcc")
+
+// Shift the last pending decision mask into the word (end of a body).
+__device__ __forceinline__ void flush_decision(uint32_t &d, uint64_t &pend) {
+  asm volatile("s_nop 1\n\t"
+               "v_addc_co_u32 %[d], vcc, %[d], %[d], %[pd]"
+               : [d] "+v"(d)
+               : [pd] "s"(pend)
+               : "vcc");
+  pend = 0;
+}
 
 #define VIT_DPP_Q0 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
 #define VIT_DPP_Q1 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
@@ -151,15 +156,15 @@ __device__ __forceinline__ int parity32(uint32_t x) { return __builtin_popcount(
 #define VIT_DPP_Q3 "row_ror:8 row_mask:0xf bank_mask:0xf"
 
 template <int Q, bool NEG, bool STD>
-__device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, float s, float c, float y,
-                                         int xor32_addr) {
+__device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, uint64_t &pend, float s, float c,
+                                         float y, int xor32_addr) {
   float B;
   if constexpr (Q < 4) {
-#define VIT_DISPATCH_DPP(DPPSTR)                                        \
-  if constexpr (STD) {                                                  \
-    if constexpr (NEG) VIT_ACS_DPP_STD(DPPSTR, "-"); else VIT_ACS_DPP_STD(DPPSTR, ""); \
-  } else {                                                              \
-    if constexpr (NEG) VIT_ACS_DPP_GEN(DPPSTR, "-"); else VIT_ACS_DPP_GEN(DPPSTR, ""); \
+#define VIT_DISPATCH_DPP(DPPSTR)                                                            \
+  if constexpr (STD) {                                                                      \
+    if constexpr (NEG) VIT_ACS_DPP(DPPSTR, "-", "-%[x]"); else VIT_ACS_DPP(DPPSTR, "", "-%[x]"); \
+  } else {                                                                                  \
+    if constexpr (NEG) VIT_ACS_DPP(DPPSTR, "-", "%[y]"); else VIT_ACS_DPP(DPPSTR, "", "%[y]");   \
   }
     if constexpr (Q == 0) { VIT_DISPATCH_DPP(VIT_DPP_Q0) }
     else if constexpr (Q == 1) { VIT_DISPATCH_DPP(VIT_DPP_Q1) }
@@ -167,24 +172,31 @@ __device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, float 
     else { VIT_DISPATCH_DPP(VIT_DPP_Q3) }
 #undef VIT_DISPATCH_DPP
   } else {
-    float p;
-    const int ob = __builtin_bit_cast(int, o);
+    (void)xor32_addr;
     if constexpr (Q == 4) {
-      p = __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(ob, 0x401F));  // lane ^ 16
+      if constexpr (STD) {
+        if constexpr (NEG) VIT_ACS_PERM("v_permlane16_swap_b32", "-", "-%[x]");
+        else VIT_ACS_PERM("v_permlane16_swap_b32", "", "-%[x]");
+      } else {
+        if constexpr (NEG) VIT_ACS_PERM("v_permlane16_swap_b32", "-", "%[y]");
+        else VIT_ACS_PERM("v_permlane16_swap_b32", "", "%[y]");
+      }
     } else {
-      p = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(xor32_addr, ob));  // lane ^ 32
-    }
-    if constexpr (STD) {
-      if constexpr (NEG) VIT_ACS_P("-", "-%[x]"); else VIT_ACS_P("", "-%[x]");
-    } else {
-      if constexpr (NEG) VIT_ACS_P("-", "%[y]"); else VIT_ACS_P("", "%[y]");
+      if constexpr (STD) {
+        if constexpr (NEG) VIT_ACS_PERM("v_permlane32_swap_b32", "-", "-%[x]");
+        else VIT_ACS_PERM("v_permlane32_swap_b32", "", "-%[x]");
+      } else {
+        if constexpr (NEG) VIT_ACS_PERM("v_permlane32_swap_b32", "-", "%[y]");
+        else VIT_ACS_PERM("v_permlane32_swap_b32", "", "%[y]");
+      }
     }
   }
 }
 
 template <bool NA, bool NB, bool STD>
 __device__ __forceinline__ void acs_pair(float &oa, float &ob, float &xa, float &xb, uint32_t &da,
-                                         uint32_t &db, float s, float ca, float cb, float ya, float yb) {
+                                         uint32_t &db, uint64_t &pa, uint64_t &pb, float s, float ca, float cb,
+                                         float ya, float yb) {
   float Ba, Bb;
 #define VIT_PAIR_SIGNS(BTA, BTB)                                             \
   if constexpr (NA && NB) VIT_ACS_PAIR("-", "-", BTA, BTB);                  \
@@ -222,6 +234,7 @@ struct Decoder {
   // per-block state
   float o[REGS];
   uint32_t dec[REGS];
+  uint64_t pend[REGS];       // compare mask of the last stage, not yet in dec
   float xn[REGS], yn[REGS];  // branch metrics prefetched for the next step
   int table;
   int nxt[BETA];         // raw LLR words of the next tile (float bits or sign-extended int8)
@@ -377,7 +390,10 @@ struct Decoder {
     }
     if constexpr (G == BODY - 1) {
 #pragma unroll
-      for (int reg = 0; reg < REGS; ++reg) lds[(body * REGS + reg) * 64 + slot0] = dec[reg];
+      for (int reg = 0; reg < REGS; ++reg) {
+        flush_decision(dec[reg], pend[reg]);
+        lds[(body * REGS + reg) * 64 + slot0] = dec[reg];
+      }
     }
   }
 
@@ -387,8 +403,8 @@ struct Decoder {
 #pragma unroll
     for (int r = 0; r < REGS; ++r) {
       if (r == reg) {
-        if (reg_neg<P>(Q, r)) acs_lane<Q, true, STD>(o[r], x, dec[r], sgn[Q], cmed[Q], y, xor32_addr);
-        else acs_lane<Q, false, STD>(o[r], x, dec[r], sgn[Q], cmed[Q], y, xor32_addr);
+        if (reg_neg<P>(Q, r)) acs_lane<Q, true, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y, xor32_addr);
+        else acs_lane<Q, false, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y, xor32_addr);
       }
     }
   }
@@ -400,10 +416,10 @@ struct Decoder {
       if (r == ra) {
         const bool na = reg_neg<P>(Q, ra), nb = reg_neg<P>(Q, rb);
         const float cpos = INFINITY, cneg = -INFINITY;
-        if (na && nb) acs_pair<true, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
-        else if (na) acs_pair<true, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
-        else if (nb) acs_pair<false, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
-        else acs_pair<false, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], sgn[Q], cpos, cneg, ya, yb);
+        if (na && nb) acs_pair<true, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], pend[ra], pend[rb], sgn[Q], cpos, cneg, ya, yb);
+        else if (na) acs_pair<true, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], pend[ra], pend[rb], sgn[Q], cpos, cneg, ya, yb);
+        else if (nb) acs_pair<false, true, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], pend[ra], pend[rb], sgn[Q], cpos, cneg, ya, yb);
+        else acs_pair<false, false, STD>(o[ra], o[rb], xa, xb, dec[ra], dec[rb], pend[ra], pend[rb], sgn[Q], cpos, cneg, ya, yb);
       }
     }
   }
@@ -485,6 +501,7 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
         const bool neg = (slot >> qm1) & 1;
         D.o[reg] = (start_known && slot != 0) ? (neg ? INFINITY : -INFINITY) : 0.0f;
         D.dec[reg] = 0u;
+        D.pend[reg] = 0u;
       }
     }
     // Pipeline prologue for the entry step r: metric table of its tile, raw
@@ -558,9 +575,14 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
 #pragma unroll
         for (int rr = 1; rr < REGS; ++rr)
           if ((lam >> 6) == rr) w = __builtin_amdgcn_readlane(dv[rr], lam & 63);
-        const uint32_t d = (w >> (BODY - 1 - pos)) & 1u;
-        acc = (acc << 1) | d;
-        lam = (int)(((uint32_t)lam & ~(1u << q)) | (d << q));
+        // decision bit (BODY-1-pos) of w moved straight to bit q of the slot index
+        const int sh = BODY - 1 - pos - q;
+        const uint32_t dq = (sh >= 0 ? (w >> sh) : (w << -sh)) & (1u << q);
+        lam = (int)(((uint32_t)lam & ~(1u << q)) | dq);
+        // after the k-1 stages of a phase period, bit q of the slot index holds
+        // the decision of offset pos + q: the slot index is that period's slice
+        // of the decision stream
+        if (q == 0) acc |= ((uint32_t)lam & (uint32_t)(S - 1)) << pos;
       }
       D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
     }
