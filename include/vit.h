@@ -102,6 +102,15 @@ int vit_decode(const vit_code *code, const float *llr, int64_t n, int32_t L, int
 int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v,
                   int32_t tie_rule, uint8_t *out_bits, const vit_opts *opts);
 
+/* int8 quantisation of soft inputs (the input stage of the int8 decode path;
+ * the paper does not fix one): q[i] = clamp(round_half_even(llr[i] * scale),
+ * -127, 127), the product rounded once to fp32.  -128 is never produced.
+ * llr (count floats) and q (count bytes) are device memory; asynchronous on
+ * `stream` (hipStream_t, NULL = default).  LLRs must be finite.
+ * Errors: VIT_EINVAL for count < 0, NULL buffers, or a scale that is not
+ * positive and finite; VIT_EDEVICE for launch failures. */
+int vit_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q, void *stream);
+
 /* Default options: FP32, terminated, v1 = floor(v/2), default stream. */
 vit_opts vit_opts_default(void);
 

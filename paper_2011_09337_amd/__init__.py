@@ -8,9 +8,9 @@ PyTorch provides device memory and streams.
 from . import _lib
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
-                   vit_last_error, vit_opts_default, vit_query_geometry)
+                   vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
 
-__all__ = ["decode", "make_code", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
+__all__ = ["decode", "quantize", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
            "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8",
            "VIT_TIE_LOWER_PRED"]
@@ -47,4 +47,18 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=Non
         stream = torch.cuda.current_stream(llr.device)
     opts.stream = stream.cuda_stream
     vit_decode_ex(code, llr.data_ptr(), int(n), int(L), int(v), VIT_TIE_LOWER_PRED, out.data_ptr(), opts)
+    return out
+
+
+def quantize(llr, scale, *, out=None, stream=None):
+    """int8 quantisation of a float32 device tensor (see vit_quantize_i8)."""
+    import torch
+
+    if not llr.is_cuda or not llr.is_contiguous() or llr.dtype != torch.float32:
+        raise ValueError("llr must be a contiguous float32 device tensor")
+    if out is None:
+        out = torch.empty(llr.numel(), dtype=torch.int8, device=llr.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(llr.device)
+    vit_quantize_i8(llr.data_ptr(), llr.numel(), float(scale), out.data_ptr(), stream.cuda_stream)
     return out

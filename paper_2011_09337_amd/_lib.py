@@ -63,6 +63,8 @@ lib.vit_opts_default.restype = vit_opts
 lib.vit_query_geometry.argtypes = [C.POINTER(vit_code), C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(vit_geometry)]
 lib.vit_query_geometry.restype = C.c_int
+lib.vit_quantize_i8.argtypes = [_P, C.c_int64, C.c_float, _P, _P]
+lib.vit_quantize_i8.restype = C.c_int
 lib.vit_last_error.argtypes = []
 lib.vit_last_error.restype = C.c_char_p
 lib.vit_abi_version.argtypes = []
@@ -103,6 +105,10 @@ def vit_decode(code, llr_ptr, n, L, v, tie_rule, out_ptr):
 def vit_decode_ex(code, llr_ptr, n, L, v, tie_rule, out_ptr, opts=None):
     return _check(lib.vit_decode_ex(C.byref(code), llr_ptr, n, L, v, tie_rule, out_ptr,
                                     C.byref(opts) if opts is not None else None))
+
+
+def vit_quantize_i8(llr_ptr, count, scale, q_ptr, stream=None):
+    return _check(lib.vit_quantize_i8(llr_ptr, count, scale, q_ptr, stream))
 
 
 def vit_query_geometry(code, n, L, v, v1=-1, terminated=1):

@@ -134,6 +134,10 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
   if (st) return st;
   if (L > 0 && (L % 8) != 0) return fail(VIT_EUNSUPPORTED, "L = %d must be a multiple of 8", L);
+  // the kernels address LLRs with 32-bit byte offsets inside the stream
+  const int64_t llr_bytes = g.N * code->beta * (o.llr_type == VIT_LLR_I8 ? 1 : 4);
+  if (llr_bytes >= ((int64_t)1 << 32) || g.N >= ((int64_t)1 << 31))
+    return fail(VIT_EUNSUPPORTED, "stream of %lld LLR bytes is too long (limit 2^32)", (long long)llr_bytes);
   if (o.llr_type == VIT_LLR_I8) {
     // integer metrics are exact in fp32 while |metric| < 2^24
     const int64_t bound = g.max_block_stages * 128 * code->beta;
@@ -161,6 +165,16 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   hipError_t e = vit::launch_blocked(a, (hipStream_t)o.stream, &unsupported, &why);
   if (e != hipSuccess) return fail_hip(e, "launch");
   if (unsupported) return fail(VIT_EUNSUPPORTED, "%s", why);
+  return VIT_OK;
+}
+
+int vit_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q, void *stream) {
+  t_err[0] = 0;
+  if (count < 0) return fail(VIT_EINVAL, "count = %lld must be >= 0", (long long)count);
+  if (count > 0 && (!llr || !q)) return fail(VIT_EINVAL, "NULL buffer");
+  if (!(scale > 0.0f) || scale > 3.0e38f) return fail(VIT_EINVAL, "scale must be positive and finite");
+  const hipError_t e = vit::launch_quantize(llr, count, scale, q, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "quantize launch");
   return VIT_OK;
 }
 

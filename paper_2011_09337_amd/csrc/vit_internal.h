@@ -35,4 +35,7 @@ int64_t lds_bytes_per_block(int k, int beta, int64_t max_block_stages);
 hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsupported,
                           const char **why);
 
+// Launch the int8 quantiser (vit_quantize.hip) on `stream`.
+hipError_t launch_quantize(const float *llr, int64_t count, float scale, int8_t *q, hipStream_t stream);
+
 }  // namespace vit

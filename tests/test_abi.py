@@ -138,3 +138,18 @@ def test_config1_block_count_and_stages(vit):
     # 4096 bits, L = 256, v = 42 -> v1 = v2 = 21: 16 blocks, 4732 stages in all
     g = vit.vit_query_geometry(_code(vit), 4096, 256, 42, -1, 1)
     assert (g.n_blocks, g.v1, g.v2, g.stages_total) == (16, 21, 21, 4732)
+
+
+def test_quantize_argument_errors(vit):
+    E = vit.VIT_EINVAL
+    _expect(vit, E, vit.vit_quantize_i8, FAKE, -1, 1.0, FAKE)
+    _expect(vit, E, vit.vit_quantize_i8, None, 10, 1.0, FAKE)
+    _expect(vit, E, vit.vit_quantize_i8, FAKE, 10, 1.0, None)
+    _expect(vit, E, vit.vit_quantize_i8, FAKE, 10, 0.0, FAKE)
+    _expect(vit, E, vit.vit_quantize_i8, FAKE, 10, float("nan"), FAKE)
+    _expect(vit, E, vit.vit_quantize_i8, FAKE, 10, -2.0, FAKE)
+
+
+def test_stream_length_limit(vit):
+    # 32-bit byte offsets inside a stream: 2^30 stages of fp32 r1/2 are refused
+    _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode, _code(vit), FAKE, 1 << 30, 256, 35, 0, FAKE)
