@@ -129,6 +129,72 @@ typedef struct {
 int vit_query_geometry(const vit_code *code, int64_t n, int32_t L, int32_t v, int32_t v1,
                        int32_t terminated, vit_geometry *geo);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent frames (each its own stream, Sec. III applied per frame),
+ * possibly of different codes and lengths, decoded by one graph launch: one
+ * persistent kernel per code pulls the frames' blocks from a cost-sorted work
+ * list (longest first) through an atomic counter.  Results are identical, bit
+ * for bit, to decoding each frame alone with vit_decode_ex and the same
+ * (L, v, v1). */
+
+/* One frame of a batch. */
+typedef struct {
+  int32_t code_id;     /* index into the codes array of the call                   */
+  int32_t terminated;  /* 1: k-1 tail stages follow the n information stages       */
+  int64_t n;           /* information bits, > 0                                    */
+  int64_t llr_off;     /* element offset of the frame's first LLR in the batch LLRs */
+  int64_t out_off;     /* byte offset of the frame's first decoded byte            */
+} vit_frame;
+
+/* Block shape for one code of a batch. */
+typedef struct {
+  int32_t L;                /* core bits per block: a positive multiple of 8     */
+  int32_t v;                /* total overlap, >= 0                               */
+  int32_t v1;               /* left overlap, -1 = floor(v/2)                     */
+  int32_t waves_per_block;  /* waves per workgroup, 1..4                         */
+} vit_tuning;
+
+/* A plan owns pinned host staging for work lists, a captured hipGraph that is
+ * reused while the buffers and shapes stay the same, and the autotuner's
+ * choices.  It never allocates device memory: the caller supplies the
+ * workspace.  A plan is not thread-safe; distinct plans are independent. */
+typedef struct vit_plan vit_plan;
+
+int vit_plan_create(vit_plan **plan);
+void vit_plan_destroy(vit_plan *plan);
+
+/* Device workspace bytes that vit_decode_batch needs for these frames.  With
+ * tune = NULL the size covers every shape the autotuner may choose. */
+int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                             const vit_tuning *tune, size_t *bytes);
+
+/* Decode a batch.  codes: ncodes (1..8) codes; frames: host array; llr: device
+ * buffer of llr_count elements of llr_type; out: device buffer of out_bytes
+ * bytes (frames' output ranges must not overlap); tune: one vit_tuning per
+ * code, or NULL for the plan's autotuned shapes (default L = 256, v = 5k,
+ * 1 wave per workgroup when not tuned); workspace: device memory of at least
+ * vit_batch_workspace_size bytes, 256-byte aligned, not used by concurrent
+ * calls.  Asynchronous on `stream`; the host staging of the previous use of
+ * a staging slot is waited for before it is rewritten.
+ * Errors: VIT_EINVAL for bad codes, frames outside the buffers, bad tunings
+ * or a small workspace; VIT_EUNSUPPORTED for shapes without a kernel (LDS);
+ * VIT_EDEVICE for HIP failures. */
+int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                     int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                     int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/* Autotune: for each code, time the batch's frames of that code with every
+ * candidate shape (L in {64, 128, 256, 512, 1024}, v = 5k, v1 = floor(v/2),
+ * 1 or 2 waves per workgroup) and keep the fastest in the plan, keyed by
+ * (code, llr_type, frame-length bucket).  chosen (may be NULL) receives one
+ * vit_tuning per code.  Same buffers and errors as vit_decode_batch; the
+ * output buffer holds the last candidate's result afterwards. */
+int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                      int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                      int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream,
+                      vit_tuning *chosen);
+
 /* Thread-local description of the last error ("" if none). */
 const char *vit_last_error(void);
 

@@ -41,6 +41,15 @@ class vit_geometry(C.Structure):
                 ("lds_bytes_per_block", C.c_int64)]
 
 
+class vit_frame(C.Structure):
+    _fields_ = [("code_id", C.c_int32), ("terminated", C.c_int32), ("n", C.c_int64), ("llr_off", C.c_int64),
+                ("out_off", C.c_int64)]
+
+
+class vit_tuning(C.Structure):
+    _fields_ = [("L", C.c_int32), ("v", C.c_int32), ("v1", C.c_int32), ("waves_per_block", C.c_int32)]
+
+
 class VitError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -65,6 +74,21 @@ lib.vit_query_geometry.argtypes = [C.POINTER(vit_code), C.c_int64, C.c_int32, C.
 lib.vit_query_geometry.restype = C.c_int
 lib.vit_quantize_i8.argtypes = [_P, C.c_int64, C.c_float, _P, _P]
 lib.vit_quantize_i8.restype = C.c_int
+_PC = C.POINTER(vit_code)
+_PF = C.POINTER(vit_frame)
+_PT = C.POINTER(vit_tuning)
+lib.vit_plan_create.argtypes = [C.POINTER(C.c_void_p)]
+lib.vit_plan_create.restype = C.c_int
+lib.vit_plan_destroy.argtypes = [C.c_void_p]
+lib.vit_plan_destroy.restype = None
+lib.vit_batch_workspace_size.argtypes = [_PC, C.c_int32, _PF, C.c_int32, _PT, C.POINTER(C.c_size_t)]
+lib.vit_batch_workspace_size.restype = C.c_int
+lib.vit_decode_batch.argtypes = [C.c_void_p, _PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P,
+                                 C.c_int64, _PT, _P, C.c_size_t, _P]
+lib.vit_decode_batch.restype = C.c_int
+lib.vit_plan_autotune.argtypes = [C.c_void_p, _PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P,
+                                  C.c_int64, _P, C.c_size_t, _P, _PT]
+lib.vit_plan_autotune.restype = C.c_int
 lib.vit_last_error.argtypes = []
 lib.vit_last_error.restype = C.c_char_p
 lib.vit_abi_version.argtypes = []
@@ -115,3 +139,58 @@ def vit_query_geometry(code, n, L, v, v1=-1, terminated=1):
     g = vit_geometry()
     _check(lib.vit_query_geometry(C.byref(code), n, L, v, v1, terminated, C.byref(g)))
     return g
+
+
+def codes_array(codes):
+    arr = (vit_code * len(codes))()
+    for i, c in enumerate(codes):
+        arr[i] = c
+    return arr
+
+
+def frames_array(frames):
+    """frames: iterable of (code_id, terminated, n, llr_off, out_off)."""
+    frames = list(frames)
+    arr = (vit_frame * len(frames))()
+    for i, (cid, term, n, lo, oo) in enumerate(frames):
+        arr[i].code_id, arr[i].terminated, arr[i].n, arr[i].llr_off, arr[i].out_off = cid, term, n, lo, oo
+    return arr
+
+
+def tunings_array(tunings):
+    arr = (vit_tuning * len(tunings))()
+    for i, t in enumerate(tunings):
+        arr[i].L, arr[i].v, arr[i].v1, arr[i].waves_per_block = t
+    return arr
+
+
+def vit_plan_create():
+    p = C.c_void_p()
+    _check(lib.vit_plan_create(C.byref(p)))
+    return p
+
+
+def vit_plan_destroy(plan):
+    lib.vit_plan_destroy(plan)
+
+
+def vit_batch_workspace_size(codes_arr, frames_arr, tune_arr=None):
+    b = C.c_size_t()
+    _check(lib.vit_batch_workspace_size(codes_arr, len(codes_arr), frames_arr, len(frames_arr), tune_arr,
+                                        C.byref(b)))
+    return b.value
+
+
+def vit_decode_batch(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, tune_arr,
+                     ws_ptr, ws_bytes, stream=None):
+    return _check(lib.vit_decode_batch(plan, codes_arr, len(codes_arr), frames_arr, len(frames_arr), llr_ptr,
+                                       llr_count, llr_type, out_ptr, out_bytes, tune_arr, ws_ptr, ws_bytes,
+                                       stream))
+
+
+def vit_plan_autotune(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, ws_ptr,
+                      ws_bytes, stream=None):
+    chosen = (vit_tuning * len(codes_arr))()
+    _check(lib.vit_plan_autotune(plan, codes_arr, len(codes_arr), frames_arr, len(frames_arr), llr_ptr, llr_count,
+                                 llr_type, out_ptr, out_bytes, ws_ptr, ws_bytes, stream, chosen))
+    return [(t.L, t.v, t.v1, t.waves_per_block) for t in chosen]

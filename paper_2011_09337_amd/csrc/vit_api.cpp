@@ -13,9 +13,31 @@
 #include "vit_internal.h"
 
 namespace {
-
 thread_local char t_err[512] = "";
+}  // namespace
 
+namespace vit {
+
+void api_clear_error() { t_err[0] = 0; }
+
+int api_fail(int status, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_err, sizeof(t_err), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int api_fail_hip(hipError_t e, const char *what) {
+  return api_fail(VIT_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+}  // namespace vit
+
+namespace {
+
+using vit::api_fail;
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int status, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -24,9 +46,7 @@ int fail(int status, const char *fmt, ...) {
   return status;
 }
 
-int fail_hip(hipError_t e, const char *what) {
-  return fail(VIT_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
-}
+int fail_hip(hipError_t e, const char *what) { return vit::api_fail_hip(e, what); }
 
 int check_code(const vit_code *c) {
   if (!c) return fail(VIT_EINVAL, "code is NULL");
@@ -38,6 +58,14 @@ int check_code(const vit_code *c) {
   }
   return VIT_OK;
 }
+
+}  // namespace
+
+namespace vit {
+int api_check_code(const vit_code *c) { return check_code(c); }
+}  // namespace vit
+
+namespace {
 
 struct Geometry {
   int64_t N, L, v1, v2, nblocks, max_block_stages;

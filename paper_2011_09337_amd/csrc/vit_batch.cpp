@@ -1,0 +1,486 @@
+// vit_batch.cpp -- batched decoding of many frames (mixed codes and lengths):
+// work lists, one reusable hipGraph per plan, and the autotuner.
+//
+// A batch is cut into blocks exactly as each frame would be on its own
+// (Sec. III of the paper, per frame).  Each block is one work item; items of
+// one code are sorted by cost (stages) so the persistent waves of that code's
+// kernel take the longest first.  Per call the host writes the header (item
+// counters = 0, counts, offsets) and the items into pinned staging memory; the
+// graph copies them into the caller's device workspace and runs one kernel
+// node per code.  While the buffers, codes and shapes stay the same the graph
+// is reused and only its copy node is updated.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vit.h"
+#include "vit_internal.h"
+
+struct vit_plan {
+  void *staging[2] = {nullptr, nullptr};
+  size_t staging_cap[2] = {0, 0};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int slot = 0;
+
+  // graph cache
+  bool have_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t copy_node = nullptr;
+  struct Key {
+    const void *llr = nullptr;
+    void *out = nullptr;
+    void *ws = nullptr;
+    int llr_type = -1;
+    int ncodes = 0;
+    int dev = -1;
+    vit_code codes[vit::kMaxCodes];
+    vit_tuning tune[vit::kMaxCodes];
+  } key;
+
+  std::map<std::string, vit_tuning> tuned;
+};
+
+namespace {
+
+using vit::api_fail;
+using vit::kHeaderBytes;
+using vit::kMaxCodes;
+using vit::WorkItem;
+
+bool same_code(const vit_code &a, const vit_code &b) {
+  if (a.k != b.k || a.beta != b.beta) return false;
+  for (int i = 0; i < a.beta; ++i)
+    if (a.gen[i] != b.gen[i]) return false;
+  return true;
+}
+
+bool same_tuning(const vit_tuning &a, const vit_tuning &b) {
+  return a.L == b.L && a.v == b.v && a.v1 == b.v1 && a.waves_per_block == b.waves_per_block;
+}
+
+vit_tuning default_tuning(const vit_code &c) {
+  vit_tuning t;
+  t.L = 256;
+  t.v = 5 * c.k;
+  t.v1 = -1;
+  t.waves_per_block = 1;
+  return t;
+}
+
+int check_tuning(const vit_tuning &t) {
+  if (t.L <= 0 || t.L % 8 != 0) return api_fail(VIT_EINVAL, "tuning L = %d must be a positive multiple of 8", t.L);
+  if (t.v < 0) return api_fail(VIT_EINVAL, "tuning v = %d must be >= 0", t.v);
+  if (t.v1 < -1 || t.v1 > t.v) return api_fail(VIT_EINVAL, "tuning v1 = %d outside [-1, v]", t.v1);
+  if (t.waves_per_block < 1 || t.waves_per_block > 4)
+    return api_fail(VIT_EINVAL, "waves_per_block = %d outside [1, 4]", t.waves_per_block);
+  return VIT_OK;
+}
+
+int frame_bucket(int64_t mean_n) {
+  int b = 0;
+  while (b < 40 && ((int64_t)1 << (b + 1)) <= mean_n) ++b;
+  return b;
+}
+
+std::string tune_key(const vit_code &c, int llr_type, int bucket) {
+  char buf[128];
+  snprintf(buf, sizeof(buf), "k%d b%d g%u,%u,%u,%u t%d n%d", c.k, c.beta, c.gen[0], c.gen[1],
+           c.beta > 2 ? c.gen[2] : 0u, c.beta > 3 ? c.gen[3] : 0u, llr_type, bucket);
+  return buf;
+}
+
+int check_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes) {
+  if (!codes || ncodes < 1 || ncodes > kMaxCodes) return api_fail(VIT_EINVAL, "ncodes = %d outside [1, 8]", ncodes);
+  for (int c = 0; c < ncodes; ++c) {
+    const int st = vit::api_check_code(&codes[c]);
+    if (st) return st;
+  }
+  if (!frames || nframes < 1) return api_fail(VIT_EINVAL, "no frames");
+  return VIT_OK;
+}
+
+// Work items of every frame under the given shapes.  Returns the number of
+// items per code in counts[], fills header offsets, and (if items != NULL)
+// the items themselves, each code's run sorted by cost, longest first.
+int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                    const vit_tuning *shape, int elem_bytes, WorkItem *items, int32_t *header,
+                    int64_t *max_stages) {
+  int64_t counts[kMaxCodes] = {0};
+  for (int32_t f = 0; f < nframes; ++f) {
+    const int c = frames[f].code_id;
+    counts[c] += (frames[f].n + shape[c].L - 1) / shape[c].L;
+  }
+  int64_t offs[kMaxCodes] = {0};
+  int64_t total = 0;
+  for (int c = 0; c < ncodes; ++c) {
+    offs[c] = total;
+    total += counts[c];
+    if (max_stages) max_stages[c] = 0;
+  }
+  if (!items) return total;
+  int64_t fill[kMaxCodes];
+  for (int c = 0; c < ncodes; ++c) fill[c] = offs[c];
+  for (int32_t f = 0; f < nframes; ++f) {
+    const vit_frame &fr = frames[f];
+    const int c = fr.code_id;
+    const vit_code &code = codes[c];
+    const int64_t N = fr.n + (fr.terminated ? code.k - 1 : 0);
+    const int64_t L = shape[c].L;
+    const int64_t v1 = shape[c].v1 < 0 ? shape[c].v / 2 : shape[c].v1;
+    const int64_t v2 = shape[c].v - v1;
+    for (int64_t cs = 0; cs < fr.n; cs += L) {
+      const int64_t ce = cs + L < fr.n ? cs + L : fr.n;
+      const int64_t s = cs - v1 > 0 ? cs - v1 : 0;
+      const int64_t e = ce + v2 < N ? ce + v2 : N;
+      WorkItem &it = items[fill[c]++];
+      it.llr_off = fr.llr_off * elem_bytes;
+      it.out_off = fr.out_off;
+      it.s = (int32_t)s;
+      it.e = (int32_t)e;
+      it.cs = (int32_t)cs;
+      it.ce = (int32_t)ce;
+      it.flags = (s == 0 ? 1 : 0) | ((fr.terminated && e == N) ? 2 : 0);
+      it.cost = (int32_t)(e - s);
+      if (max_stages && e - s > max_stages[c]) max_stages[c] = e - s;
+    }
+  }
+  for (int c = 0; c < ncodes; ++c) {
+    std::stable_sort(items + offs[c], items + offs[c] + counts[c],
+                     [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
+    header[kMaxCodes + c] = (int32_t)counts[c];
+    header[2 * kMaxCodes + c] = (int32_t)offs[c];
+  }
+  return total;
+}
+
+int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes, int64_t llr_count,
+                 int llr_type, int64_t out_bytes) {
+  const int elem = llr_type == VIT_LLR_I8 ? 1 : 4;
+  std::vector<std::pair<int64_t, int64_t>> outs;
+  outs.reserve(nframes);
+  for (int32_t f = 0; f < nframes; ++f) {
+    const vit_frame &fr = frames[f];
+    if (fr.code_id < 0 || fr.code_id >= ncodes) return api_fail(VIT_EINVAL, "frame %d: code_id %d", f, fr.code_id);
+    if (fr.n <= 0) return api_fail(VIT_EINVAL, "frame %d: n = %lld", f, (long long)fr.n);
+    if (fr.terminated != 0 && fr.terminated != 1) return api_fail(VIT_EINVAL, "frame %d: terminated", f);
+    if (fr.llr_off < 0 || fr.out_off < 0) return api_fail(VIT_EINVAL, "frame %d: negative offset", f);
+    const vit_code &c = codes[fr.code_id];
+    const int64_t N = fr.n + (fr.terminated ? c.k - 1 : 0);
+    if (fr.llr_off + N * c.beta > llr_count)
+      return api_fail(VIT_EINVAL, "frame %d: LLRs [%lld, %lld) beyond the buffer (%lld)", f, (long long)fr.llr_off,
+                      (long long)(fr.llr_off + N * c.beta), (long long)llr_count);
+    if (N * c.beta * elem >= ((int64_t)1 << 31) || fr.llr_off * elem >= ((int64_t)1 << 62))
+      return api_fail(VIT_EUNSUPPORTED, "frame %d is too long", f);
+    const int64_t nb = (fr.n + 7) / 8;
+    if (fr.out_off + nb > out_bytes) return api_fail(VIT_EINVAL, "frame %d: output beyond the buffer", f);
+    outs.emplace_back(fr.out_off, fr.out_off + nb);
+  }
+  std::sort(outs.begin(), outs.end());
+  for (size_t i = 1; i < outs.size(); ++i)
+    if (outs[i].first < outs[i - 1].second) return api_fail(VIT_EINVAL, "frames' output ranges overlap");
+  return VIT_OK;
+}
+
+int resolve_shapes(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                   int llr_type, const vit_tuning *tune, vit_tuning *shape) {
+  for (int c = 0; c < ncodes; ++c) {
+    if (tune) {
+      shape[c] = tune[c];
+    } else {
+      int64_t sum = 0, cnt = 0;
+      for (int32_t f = 0; f < nframes; ++f)
+        if (frames[f].code_id == c) {
+          sum += frames[f].n;
+          ++cnt;
+        }
+      const int bucket = frame_bucket(cnt ? sum / cnt : 0);
+      auto it = plan->tuned.find(tune_key(codes[c], llr_type, bucket));
+      shape[c] = it != plan->tuned.end() ? it->second : default_tuning(codes[c]);
+    }
+    const int st = check_tuning(shape[c]);
+    if (st) return st;
+  }
+  return VIT_OK;
+}
+
+int ensure_staging(vit_plan *p, int slot, size_t bytes) {
+  if (p->staging_cap[slot] >= bytes) return VIT_OK;
+  if (p->staging[slot]) {
+    hipError_t e = hipHostFree(p->staging[slot]);
+    p->staging[slot] = nullptr;
+    p->staging_cap[slot] = 0;
+    if (e != hipSuccess) return vit::api_fail_hip(e, "hipHostFree");
+  }
+  size_t cap = 1 << 16;
+  while (cap < bytes) cap *= 2;
+  hipError_t e = hipHostMalloc(&p->staging[slot], cap, hipHostMallocDefault);
+  if (e != hipSuccess) return vit::api_fail_hip(e, "hipHostMalloc");
+  p->staging_cap[slot] = cap;
+  return VIT_OK;
+}
+
+void drop_graph(vit_plan *p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->copy_node = nullptr;
+  p->have_graph = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vit_plan_create(vit_plan **plan) {
+  vit::api_clear_error();
+  if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
+  *plan = new (std::nothrow) vit_plan();
+  if (!*plan) return api_fail(VIT_ENOMEM, "plan allocation failed");
+  return VIT_OK;
+}
+
+void vit_plan_destroy(vit_plan *plan) {
+  if (!plan) return;
+  for (int i = 0; i < 2; ++i) {
+    if (plan->done[i]) {
+      (void)hipEventSynchronize(plan->done[i]);
+      (void)hipEventDestroy(plan->done[i]);
+    }
+    if (plan->staging[i]) (void)hipHostFree(plan->staging[i]);
+  }
+  drop_graph(plan);
+  delete plan;
+}
+
+int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                             const vit_tuning *tune, size_t *bytes) {
+  vit::api_clear_error();
+  int st = check_args(codes, ncodes, frames, nframes);
+  if (st) return st;
+  if (!bytes) return api_fail(VIT_EINVAL, "bytes is NULL");
+  vit_tuning shape[kMaxCodes];
+  for (int c = 0; c < ncodes; ++c) {
+    if (tune) {
+      shape[c] = tune[c];
+      st = check_tuning(shape[c]);
+      if (st) return st;
+    } else {
+      shape[c] = default_tuning(codes[c]);
+      shape[c].L = 64;  // the smallest block the autotuner tries: the most items
+    }
+  }
+  for (int32_t f = 0; f < nframes; ++f)
+    if (frames[f].code_id < 0 || frames[f].code_id >= ncodes || frames[f].n <= 0)
+      return api_fail(VIT_EINVAL, "frame %d: bad code_id or n", f);
+  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, 4, nullptr, nullptr, nullptr);
+  *bytes = kHeaderBytes + (size_t)total * sizeof(WorkItem);
+  return VIT_OK;
+}
+
+int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                     int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                     int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
+                     void *stream) {
+  vit::api_clear_error();
+  if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
+  int st = check_args(codes, ncodes, frames, nframes);
+  if (st) return st;
+  if (!llr || !out || !workspace) return api_fail(VIT_EINVAL, "NULL buffer");
+  if (((uintptr_t)workspace & 255u) != 0) return api_fail(VIT_EINVAL, "workspace must be 256-byte aligned");
+  if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8) return api_fail(VIT_EINVAL, "unknown llr_type %d", llr_type);
+  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
+  if (st) return st;
+  vit_tuning shape[kMaxCodes];
+  st = resolve_shapes(plan, codes, ncodes, frames, nframes, llr_type, tune, shape);
+  if (st) return st;
+
+  const int elem = llr_type == VIT_LLR_I8 ? 1 : 4;
+  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, elem, nullptr, nullptr, nullptr);
+  const size_t need = kHeaderBytes + (size_t)total * sizeof(WorkItem);
+  if (workspace_bytes < need)
+    return api_fail(VIT_EINVAL, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
+  if (total >= ((int64_t)1 << 31)) return api_fail(VIT_EUNSUPPORTED, "too many blocks");
+
+  // the staging slot's previous copy must have run before it is rewritten
+  const int slot = plan->slot;
+  hipError_t he;
+  if (plan->pending[slot]) {
+    he = hipEventSynchronize(plan->done[slot]);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipEventSynchronize");
+    plan->pending[slot] = false;
+  }
+  st = ensure_staging(plan, slot, need);
+  if (st) return st;
+  char *stg = (char *)plan->staging[slot];
+  int32_t *header = (int32_t *)stg;
+  memset(header, 0, kHeaderBytes);
+  int64_t max_stages[kMaxCodes];
+  build_items(codes, ncodes, frames, nframes, shape, elem, (WorkItem *)(stg + kHeaderBytes), header, max_stages);
+
+  int dev = 0;
+  he = hipGetDevice(&dev);
+  if (he != hipSuccess) return vit::api_fail_hip(he, "hipGetDevice");
+
+  // launch shapes (LDS sized for the longest block a shape can produce)
+  vit::BatchLaunch bl[kMaxCodes];
+  for (int c = 0; c < ncodes; ++c) {
+    const int64_t vv = shape[c].v;
+    int unsupported = 0;
+    const char *why = "";
+    he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type == VIT_LLR_I8,
+                                (int64_t)shape[c].L + vv, shape[c].waves_per_block, &bl[c], &unsupported, &why);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
+    if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
+    if (llr_type == VIT_LLR_I8 && ((int64_t)shape[c].L + vv) * 128 * codes[c].beta >= ((int64_t)1 << 24))
+      return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
+  }
+
+  // graph: reuse while buffers, codes and shapes are unchanged
+  vit_plan::Key key;
+  key.llr = llr;
+  key.out = out;
+  key.ws = workspace;
+  key.llr_type = llr_type;
+  key.ncodes = ncodes;
+  key.dev = dev;
+  bool same = plan->have_graph && plan->key.llr == llr && plan->key.out == out && plan->key.ws == workspace &&
+              plan->key.llr_type == llr_type && plan->key.ncodes == ncodes && plan->key.dev == dev;
+  for (int c = 0; c < ncodes; ++c) {
+    key.codes[c] = codes[c];
+    key.tune[c] = shape[c];
+    if (same) same = same_code(plan->key.codes[c], codes[c]) && same_tuning(plan->key.tune[c], shape[c]);
+  }
+  if (!same) {
+    drop_graph(plan);
+    he = hipGraphCreate(&plan->graph, 0);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphCreate");
+    he = hipGraphAddMemcpyNode1D(&plan->copy_node, plan->graph, nullptr, 0, workspace, stg, need,
+                                 hipMemcpyHostToDevice);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddMemcpyNode1D");
+    for (int c = 0; c < ncodes; ++c) {
+      vit::BatchArgs args;
+      args.llr = llr;
+      args.out = out;
+      args.header = (int32_t *)workspace;
+      args.items = (const WorkItem *)((char *)workspace + kHeaderBytes);
+      args.code_index = c;
+      for (int b = 0; b < 4; ++b) args.gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0u;
+      int words = bl[c].lds_words_per_wave;
+      void *kargs[] = {&args, &words};
+      hipKernelNodeParams kp;
+      memset(&kp, 0, sizeof(kp));
+      kp.func = const_cast<void *>(bl[c].fn);
+      kp.gridDim = dim3(bl[c].grid);
+      kp.blockDim = dim3(bl[c].block);
+      kp.sharedMemBytes = (unsigned)bl[c].lds;
+      kp.kernelParams = kargs;
+      kp.extra = nullptr;
+      hipGraphNode_t kn;
+      he = hipGraphAddKernelNode(&kn, plan->graph, &plan->copy_node, 1, &kp);
+      if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddKernelNode");
+    }
+    he = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphInstantiate");
+    plan->key = key;
+    plan->have_graph = true;
+  } else {
+    he = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->copy_node, workspace, stg, need,
+                                           hipMemcpyHostToDevice);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphExecMemcpyNodeSetParams1D");
+  }
+  he = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphLaunch");
+  if (!plan->done[slot]) {
+    he = hipEventCreateWithFlags(&plan->done[slot], hipEventDisableTiming);
+    if (he != hipSuccess) return vit::api_fail_hip(he, "hipEventCreate");
+  }
+  he = hipEventRecord(plan->done[slot], (hipStream_t)stream);
+  if (he != hipSuccess) return vit::api_fail_hip(he, "hipEventRecord");
+  plan->pending[slot] = true;
+  plan->slot = slot ^ 1;
+  return VIT_OK;
+}
+
+int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                      int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                      int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream, vit_tuning *chosen) {
+  vit::api_clear_error();
+  if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
+  int st = check_args(codes, ncodes, frames, nframes);
+  if (st) return st;
+  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  hipError_t he = hipEventCreate(&e0);
+  if (he != hipSuccess) return vit::api_fail_hip(he, "hipEventCreate");
+  he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return vit::api_fail_hip(he, "hipEventCreate");
+  }
+  static const int kL[] = {64, 128, 256, 512, 1024};
+  int result = VIT_OK;
+  for (int c = 0; c < ncodes && result == VIT_OK; ++c) {
+    std::vector<vit_frame> sub;
+    int64_t sum = 0;
+    for (int32_t f = 0; f < nframes; ++f)
+      if (frames[f].code_id == c) {
+        sub.push_back(frames[f]);
+        sub.back().code_id = 0;
+        sum += frames[f].n;
+      }
+    vit_tuning best = default_tuning(codes[c]);
+    if (sub.empty()) {
+      if (chosen) chosen[c] = best;
+      continue;
+    }
+    float best_ms = 1e30f;
+    for (int li = 0; li < 5 && result == VIT_OK; ++li) {
+      for (int w = 1; w <= 2 && result == VIT_OK; ++w) {
+        vit_tuning t = default_tuning(codes[c]);
+        t.L = kL[li];
+        t.waves_per_block = w;
+        st = vit_decode_batch(plan, &codes[c], 1, sub.data(), (int32_t)sub.size(), llr, llr_count, llr_type, out,
+                              out_bytes, &t, workspace, workspace_bytes, stream);
+        if (st == VIT_EUNSUPPORTED) continue;  // shape does not fit: not a candidate
+        if (st) {
+          result = st;
+          break;
+        }
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        for (int rep = 0; rep < 3 && result == VIT_OK; ++rep)
+          result = vit_decode_batch(plan, &codes[c], 1, sub.data(), (int32_t)sub.size(), llr, llr_count, llr_type,
+                                    out, out_bytes, &t, workspace, workspace_bytes, stream);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        he = hipEventSynchronize(e1);
+        if (he != hipSuccess) {
+          result = vit::api_fail_hip(he, "hipEventSynchronize");
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+    if (result == VIT_OK) {
+      plan->tuned[tune_key(codes[c], llr_type, frame_bucket(sum / (int64_t)sub.size()))] = best;
+      if (chosen) chosen[c] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+}  // extern "C"

@@ -438,6 +438,147 @@ struct Decoder {
   X(B + 7, M)
 #define VIT_X32(X, M) VIT_X8(X, 0, M) VIT_X8(X, 8, M) VIT_X8(X, 16, M) VIT_X8(X, 24, M)
 
+// Decode one block (Sec. III): trellis stages [s, e) of a frame whose LLRs
+// start (stage 0) at `llr` and whose decoded bits start (bit 0) at byte `out`;
+// emit core bits [cs, ce).  start_known: the window starts at the frame's
+// first stage (state 0); end_zero: it ends at the last stage of a terminated
+// frame (trace back from state 0).  Stages are frame-local; the caller
+// guarantees (e - s) * beta * sizeof(LLR) < 2^31 and cs a multiple of 8.
+template <int K, int BETA, bool STD, bool I8>
+__device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const void *llr, uint8_t *out,
+                                             int64_t s, int64_t e, int64_t cs, int64_t ce, bool start_known,
+                                             bool end_zero, const uint32_t *gen) {
+  using Sh = Shape<K, BETA>;
+  constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
+  (void)T;
+  D.llr = llr;
+  const int M = (int)(e - s);
+  const int r = (BODY - M % BODY) % BODY;
+  const int nbody = (M + r) / BODY;
+  D.s = s;
+  D.e = e;
+  D.stage_base = s - r;
+  D.tile_stage0 = (int)(s - r) + D.tl;
+  D.s_lo = (int)s;
+  D.s_hi = (int)e - 1;
+  D.body = 0;
+
+  // Initial metrics: state 0 known at the stream start, else all zero.  The
+  // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
+  {
+    const int qm1 = (r + P - 1) % P;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int slot = ((reg << 6) | D.slot0) & (S - 1);
+      const bool neg = (slot >> qm1) & 1;
+      D.o[reg] = (start_known && slot != 0) ? (neg ? INFINITY : -INFINITY) : 0.0f;
+      D.dec[reg] = 0u;
+      D.pend[reg] = 0u;
+    }
+  }
+  // Pipeline prologue for the entry step r: metric table of its tile, raw
+  // LLRs of the next tile (the step that starts a tile loads the next one),
+  // and the entry step's own branch metrics.
+  {
+    const int tau0 = r / T;
+    D.load_tile(tau0);
+    D.build_table();
+    if (r % T != 0) D.load_tile(tau0 + 1);
+    D.body = 0;
+    D.fetch_entry(gen, r, D.xn, D.yn);
+  }
+  D.body = 0;
+  D.refresh_addresses();
+  VIT_X32(VIT_G1, BODY)
+  for (D.body = 1; D.body < nbody; ++D.body) {
+    D.refresh_addresses();
+    VIT_X32(VIT_U1, BODY)
+  }
+
+  // ---- traceback start: after M + r (a multiple of BODY) steps, slot j holds state j.
+  constexpr int qlast = (BODY - 1) % P;
+  int lam = 0;
+  if (!end_zero) {
+    float best = -INFINITY;
+    int lab = 0x7fffffff;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int slot = (reg << 6) | D.slot0;
+      const int label = slot & (S - 1);
+      const float sig = ((slot >> qlast) & 1) ? -D.o[reg] : D.o[reg];
+      if (reg == 0 || sig > best) {
+        best = sig;
+        lab = label;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const float ob = __shfl_xor(best, m);
+      const int ol = __shfl_xor(lab, m);
+      if (ob > best || (ob == best && ol < lab)) {
+        best = ob;
+        lab = ol;
+      }
+    }
+    lam = __builtin_amdgcn_readfirstlane(lab);
+  }
+
+  // ---- traceback (Algorithm 2) on the scalar unit.  lam is the slot index
+  // of the current state; the decision words are stored by slot, so its
+  // decision bit is bit (BODY-1-pos) of lane lam & 63 of register lam >> 6.
+  // Following the survivor replaces bit q = (body offset) mod (k-1) of the
+  // slot index with that decision bit.  The decision bit read at body offset
+  // g is the input bit of offset g - (k-1) (the oldest input of the state),
+  // so the decision stream, followed by the k-1 bits of the start slot, is
+  // the decoded sequence shifted by k-1: bit t of the output is stream bit
+  // (t - stage_base) + k - 1.  Each group's 32-bit stream word replaces the
+  // first decision dword of its group in LDS.
+  const uint32_t lam_start = (uint32_t)lam;
+  const int grp_lo = ((int)(cs - s) + r) / BODY;
+  for (int grp = nbody - 1; grp >= grp_lo; --grp) {
+    uint32_t dv[REGS];
+#pragma unroll
+    for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int pos = BODY - 1; pos >= 0; --pos) {
+      const int q = pos % P;
+      uint32_t w = __builtin_amdgcn_readlane(dv[0], lam & 63);
+#pragma unroll
+      for (int rr = 1; rr < REGS; ++rr)
+        if ((lam >> 6) == rr) w = __builtin_amdgcn_readlane(dv[rr], lam & 63);
+      // decision bit (BODY-1-pos) of w moved straight to bit q of the slot index
+      const int sh = BODY - 1 - pos - q;
+      const uint32_t dq = (sh >= 0 ? (w >> sh) : (w << -sh)) & (1u << q);
+      lam = (int)(((uint32_t)lam & ~(1u << q)) | dq);
+      // after the k-1 stages of a phase period, bit q of the slot index holds
+      // the decision of offset pos + q: the slot index is that period's slice
+      // of the decision stream
+      if (q == 0) acc |= ((uint32_t)lam & (uint32_t)(S - 1)) << pos;
+    }
+    D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
+  }
+
+  // ---- output: lane-parallel assembly of the core bits [cs, ce) into bytes.
+  {
+    const int64_t b_lo = cs >> 3, b_hi = (ce - 1) >> 3;
+    const uint32_t body_mask = BODY == 32 ? 0xffffffffu : ((1u << BODY) - 1u);
+    for (int64_t B = b_lo + D.lane; B <= b_hi; B += 64) {
+      const int gbit = (int)(8 * B - D.stage_base) + P;  // stream index of the byte's bit 0
+      const int wa_i = gbit / BODY, sh = gbit - wa_i * BODY;
+      auto word = [&](int i) -> uint64_t {
+        if (i < nbody) return D.lds[(i * REGS) * 64] & body_mask;
+        return i == nbody ? lam_start : 0u;
+      };
+      const uint64_t cat = word(wa_i) | (word(wa_i + 1) << BODY);
+      uint32_t byte = (uint32_t)(cat >> sh) & 0xffu;
+      const int64_t nvalid = ce - 8 * B;
+      if (nvalid < 8) byte &= (1u << nvalid) - 1u;
+      out[B] = (uint8_t)byte;
+    }
+  }
+}
+
 template <int K, int BETA, bool STD, bool I8>
 __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, I8>;
@@ -452,7 +593,6 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
   D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
-  D.llr = a.llr;
 
   // Blocks per wave, mapped so that neighbouring blocks (which share LLR
   // overlap) run on the same XCD: workgroups are dealt round-robin to the 8
@@ -478,133 +618,33 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
     const int64_t ce = (cs + a.L < a.n) ? cs + a.L : a.n;
     const int64_t s = (cs - a.v1 > 0) ? cs - a.v1 : 0;
     const int64_t e = (ce + a.v2 < a.N) ? ce + a.v2 : a.N;
-    const int M = (int)(e - s);
-    const int r = (BODY - M % BODY) % BODY;
-    const int nbody = (M + r) / BODY;
-    const bool start_known = (s == 0);
-    const bool end_zero = a.terminated && (e == a.N);
-    D.s = s;
-    D.e = e;
-    D.stage_base = s - r;
-    D.tile_stage0 = (int)(s - r) + D.tl;
-    D.s_lo = (int)s;
-    D.s_hi = (int)e - 1;
-    D.body = 0;
+    decode_block(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.gen);
+  }
+}
 
-    // Initial metrics: state 0 known at the stream start, else all zero.  The
-    // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
-    {
-      const int qm1 = (r + P - 1) % P;
-#pragma unroll
-      for (int reg = 0; reg < REGS; ++reg) {
-        const int slot = ((reg << 6) | D.slot0) & (S - 1);
-        const bool neg = (slot >> qm1) & 1;
-        D.o[reg] = (start_known && slot != 0) ? (neg ? INFINITY : -INFINITY) : 0.0f;
-        D.dec[reg] = 0u;
-        D.pend[reg] = 0u;
-      }
-    }
-    // Pipeline prologue for the entry step r: metric table of its tile, raw
-    // LLRs of the next tile (the step that starts a tile loads the next one),
-    // and the entry step's own branch metrics.
-    {
-      const int tau0 = r / T;
-      D.load_tile(tau0);
-      D.build_table();
-      if (r % T != 0) D.load_tile(tau0 + 1);
-      D.body = 0;
-      D.fetch_entry(a.gen, r, D.xn, D.yn);
-    }
-    D.body = 0;
-    D.refresh_addresses();
-    VIT_X32(VIT_G1, BODY)
-    for (D.body = 1; D.body < nbody; ++D.body) {
-      D.refresh_addresses();
-      VIT_X32(VIT_U1, BODY)
-    }
-
-    // ---- traceback start: after M + r (a multiple of BODY) steps, slot j holds state j.
-    constexpr int qlast = (BODY - 1) % P;
-    int lam = 0;
-    if (!end_zero) {
-      float best = -INFINITY;
-      int lab = 0x7fffffff;
-#pragma unroll
-      for (int reg = 0; reg < REGS; ++reg) {
-        const int slot = (reg << 6) | D.slot0;
-        const int label = slot & (S - 1);
-        const float sig = ((slot >> qlast) & 1) ? -D.o[reg] : D.o[reg];
-        if (reg == 0 || sig > best) {
-          best = sig;
-          lab = label;
-        }
-      }
-#pragma unroll
-      for (int m = 1; m < 64; m <<= 1) {
-        const float ob = __shfl_xor(best, m);
-        const int ol = __shfl_xor(lab, m);
-        if (ob > best || (ob == best && ol < lab)) {
-          best = ob;
-          lab = ol;
-        }
-      }
-      lam = __builtin_amdgcn_readfirstlane(lab);
-    }
-
-    // ---- traceback (Algorithm 2) on the scalar unit.  lam is the slot index
-    // of the current state; the decision words are stored by slot, so its
-    // decision bit is bit (BODY-1-pos) of lane lam & 63 of register lam >> 6.
-    // Following the survivor replaces bit q = (body offset) mod (k-1) of the
-    // slot index with that decision bit.  The decision bit read at body offset
-    // g is the input bit of offset g - (k-1) (the oldest input of the state),
-    // so the decision stream, followed by the k-1 bits of the start slot, is
-    // the decoded sequence shifted by k-1: bit t of the output is stream bit
-    // (t - stage_base) + k - 1.  Each group's 32-bit stream word replaces the
-    // first decision dword of its group in LDS.
-    const uint32_t lam_start = (uint32_t)lam;
-    const int grp_lo = ((int)(cs - s) + r) / BODY;
-    for (int grp = nbody - 1; grp >= grp_lo; --grp) {
-      uint32_t dv[REGS];
-#pragma unroll
-      for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
-      uint32_t acc = 0;
-#pragma unroll
-      for (int pos = BODY - 1; pos >= 0; --pos) {
-        const int q = pos % P;
-        uint32_t w = __builtin_amdgcn_readlane(dv[0], lam & 63);
-#pragma unroll
-        for (int rr = 1; rr < REGS; ++rr)
-          if ((lam >> 6) == rr) w = __builtin_amdgcn_readlane(dv[rr], lam & 63);
-        // decision bit (BODY-1-pos) of w moved straight to bit q of the slot index
-        const int sh = BODY - 1 - pos - q;
-        const uint32_t dq = (sh >= 0 ? (w >> sh) : (w << -sh)) & (1u << q);
-        lam = (int)(((uint32_t)lam & ~(1u << q)) | dq);
-        // after the k-1 stages of a phase period, bit q of the slot index holds
-        // the decision of offset pos + q: the slot index is that period's slice
-        // of the decision stream
-        if (q == 0) acc |= ((uint32_t)lam & (uint32_t)(S - 1)) << pos;
-      }
-      D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
-    }
-
-    // ---- output: lane-parallel assembly of the core bits [cs, ce) into bytes.
-    {
-      const int64_t b_lo = cs >> 3, b_hi = (ce - 1) >> 3;
-      const uint32_t body_mask = BODY == 32 ? 0xffffffffu : ((1u << BODY) - 1u);
-      for (int64_t B = b_lo + D.lane; B <= b_hi; B += 64) {
-        const int gbit = (int)(8 * B - D.stage_base) + P;  // stream index of the byte's bit 0
-        const int wa_i = gbit / BODY, sh = gbit - wa_i * BODY;
-        auto word = [&](int i) -> uint64_t {
-          if (i < nbody) return D.lds[(i * REGS) * 64] & body_mask;
-          return i == nbody ? lam_start : 0u;
-        };
-        const uint64_t cat = word(wa_i) | (word(wa_i + 1) << BODY);
-        uint32_t byte = (uint32_t)(cat >> sh) & 0xffu;
-        const int64_t nvalid = ce - 8 * B;
-        if (nvalid < 8) byte &= (1u << nvalid) - 1u;
-        a.out[B] = (uint8_t)byte;
-      }
-    }
+// Batched decode: persistent waves pull work items (one block of one frame
+// each, sorted by cost on the host) through an atomic counter until the list
+// is exhausted.  The counter and item count live in the caller's workspace.
+template <int K, int BETA, bool STD, bool I8>
+__global__ __launch_bounds__(256) void vit_batch_kernel(BatchArgs a, int lds_words_per_wave) {
+  using Dec = Decoder<K, BETA, STD, I8>;
+  extern __shared__ uint32_t vit_lds[];
+  Dec D;
+  D.setup(a.gen);
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
+  const int nitems = a.header[kMaxCodes + a.code_index];
+  const WorkItem *items = a.items + a.header[2 * kMaxCodes + a.code_index];
+  int32_t *counter = a.header + a.code_index;
+  for (;;) {
+    int idx = 0;
+    if (D.lane == 0) idx = atomicAdd(counter, 1);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= nitems) break;
+    const WorkItem it = items[idx];
+    const char *base = (const char *)a.llr + it.llr_off;
+    decode_block(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,
+                 (it.flags & 2) != 0, a.gen);
   }
 }
 
@@ -616,6 +656,7 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
 }  // namespace dev
 
 typedef void (*KernelFn)(DecodeArgs, int);
+typedef void (*BatchKernelFn)(BatchArgs, int);
 
 // Kernel instance for (K, beta, standard code, int8 input).
 template <int K>
@@ -633,6 +674,21 @@ KernelFn pick_kernel_k(int beta, bool stdc, bool i8) {
   return nullptr;
 }
 
+template <int K>
+BatchKernelFn pick_batch_kernel_k(int beta, bool stdc, bool i8) {
+  auto pick = [&](auto bt) -> BatchKernelFn {
+    constexpr int B = decltype(bt)::value;
+    if (stdc) return i8 ? dev::vit_batch_kernel<K, B, true, true> : dev::vit_batch_kernel<K, B, true, false>;
+    return i8 ? dev::vit_batch_kernel<K, B, false, true> : dev::vit_batch_kernel<K, B, false, false>;
+  };
+  switch (beta) {
+    case 2: return pick(std::integral_constant<int, 2>{});
+    case 3: return pick(std::integral_constant<int, 3>{});
+    case 4: return pick(std::integral_constant<int, 4>{});
+  }
+  return nullptr;
+}
+
 KernelFn pick_kernel_k3(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k4(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k5(int beta, bool stdc, bool i8);
@@ -640,5 +696,12 @@ KernelFn pick_kernel_k6(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k7(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k8(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k9(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k4(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k5(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k6(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k7(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k8(int beta, bool stdc, bool i8);
+BatchKernelFn pick_batch_kernel_k9(int beta, bool stdc, bool i8);
 
 }  // namespace vit

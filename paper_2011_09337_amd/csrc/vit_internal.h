@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vit.h"
+
 namespace vit {
 
 // Arguments of one blocked decode, resolved by the host (geometry already
@@ -24,6 +26,32 @@ struct DecodeArgs {
   int32_t max_block_stages;
 };
 
+// One work item of a batched decode: one block of one frame.
+struct WorkItem {
+  int64_t llr_off;       // byte offset of the frame's first LLR in the batch buffer
+  int64_t out_off;       // byte offset of the frame's first decoded byte
+  int32_t s, e;          // frame-local stage window
+  int32_t cs, ce;        // frame-local core bits
+  int32_t flags;         // bit 0: window starts at stage 0; bit 1: ends at the last stage of a terminated frame
+  int32_t cost;          // stages x states / 64 (for sorting)
+};
+
+// Workspace header of a batched decode (device, int32 words): for code c,
+// [c] = next item to take (0 at launch), [kMaxCodes + c] = number of items,
+// [2*kMaxCodes + c] = offset of its first item in the item array.
+constexpr int kMaxCodes = 8;
+constexpr size_t kHeaderBytes = 256;
+
+// Kernel arguments of a batched decode for one code.
+struct BatchArgs {
+  const void *llr;           // device, the batch's LLR buffer
+  uint8_t *out;              // device, the batch's output buffer
+  int32_t *header;           // device, workspace header
+  const WorkItem *items;     // device, all work items (each code's run is cost-descending)
+  int32_t code_index;
+  uint32_t gen[4];
+};
+
 // Survivor (decision) storage of one block in LDS, in bytes, for a kernel
 // instance: groups of 32 stages x states/8 bytes, rounded up to whole bodies
 // of the unrolled loop.  0 if (k, beta) has no kernel instance.
@@ -34,6 +62,25 @@ int64_t lds_bytes_per_block(int k, int beta, int64_t max_block_stages);
 // or the LDS need exceeds the device limit.
 hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsupported,
                           const char **why);
+
+// Kernel instance and launch shape of a batched decode for one code.
+struct BatchLaunch {
+  const void *fn;            // __global__ function
+  unsigned grid, block;      // workgroups, threads per workgroup
+  size_t lds;                // dynamic LDS bytes per workgroup
+  int lds_words_per_wave;
+};
+// Fill *bl for a code (k, beta, generators, int8?) decoding blocks of at most
+// max_block_stages stages with `wpb` waves per workgroup.  Returns hipSuccess;
+// sets *unsupported when the shape is not available.
+hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, bool i8, int64_t max_block_stages, int wpb,
+                             BatchLaunch *bl, int *unsupported, const char **why);
+
+// Error reporting shared by the C ABI translation units (thread-local message).
+void api_clear_error();
+int api_fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int api_fail_hip(hipError_t e, const char *what);
+int api_check_code(const vit_code *c);
 
 // Launch the int8 quantiser (vit_quantize.hip) on `stream`.
 hipError_t launch_quantize(const float *llr, int64_t count, float scale, int8_t *q, hipStream_t stream);

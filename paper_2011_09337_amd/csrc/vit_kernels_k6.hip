@@ -1,6 +1,7 @@
-// vit_kernels_k6.hip -- kernel instances for constraint length k = 6.
+// vit_kernels_k6.hip -- kernel instances (stream and batch) for constraint length k = 6.
 #include "vit_decoder.h"
 
 namespace vit {
 KernelFn pick_kernel_k6(int beta, bool stdc, bool i8) { return pick_kernel_k<6>(beta, stdc, i8); }
+BatchKernelFn pick_batch_kernel_k6(int beta, bool stdc, bool i8) { return pick_batch_kernel_k<6>(beta, stdc, i8); }
 }  // namespace vit

@@ -92,4 +92,58 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   return hipGetLastError();
 }
 
+hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, bool i8, int64_t max_block_stages, int wpb,
+                             BatchLaunch *bl, int *unsupported, const char **why) {
+  *unsupported = 0;
+  bool stdc = true;
+  for (int b = 0; b < beta; ++b) stdc = stdc && ((gen[b] >> (k - 1)) & 1u) && (gen[b] & 1u);
+  BatchKernelFn fn = nullptr;
+  switch (k) {
+    case 3: fn = pick_batch_kernel_k3(beta, stdc, i8); break;
+    case 4: fn = pick_batch_kernel_k4(beta, stdc, i8); break;
+    case 5: fn = pick_batch_kernel_k5(beta, stdc, i8); break;
+    case 6: fn = pick_batch_kernel_k6(beta, stdc, i8); break;
+    case 7: fn = pick_batch_kernel_k7(beta, stdc, i8); break;
+    case 8: fn = pick_batch_kernel_k8(beta, stdc, i8); break;
+    case 9: fn = pick_batch_kernel_k9(beta, stdc, i8); break;
+  }
+  if (!fn) {
+    *unsupported = 1;
+    *why = "no batch kernel instance for this (k, beta)";
+    return hipSuccess;
+  }
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if (t_dev.dev != dev) {
+    err = hipDeviceGetAttribute(&t_dev.num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err != hipSuccess) return err;
+    err = hipDeviceGetAttribute(&t_dev.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (err != hipSuccess) return err;
+    t_dev.dev = dev;
+  }
+  const int64_t lds_wave = lds_bytes_per_block(k, beta, max_block_stages);
+  const size_t lds = (size_t)lds_wave * wpb;
+  if ((int64_t)lds > t_dev.max_lds) {
+    *unsupported = 1;
+    *why = "a block's survivor storage exceeds the per-workgroup LDS";
+    return hipSuccess;
+  }
+  if (lds > 65536) {
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  int occ = 0;
+  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(fn), 64 * wpb, lds);
+  if (err != hipSuccess) return err;
+  if (occ < 1) occ = 1;
+  bl->fn = reinterpret_cast<const void *>(fn);
+  bl->grid = (unsigned)(occ * t_dev.num_cu);
+  bl->block = (unsigned)(64 * wpb);
+  bl->lds = lds;
+  bl->lds_words_per_wave = (int)(lds_wave / 4);
+  return hipSuccess;
+}
+
 }  // namespace vit

@@ -153,3 +153,56 @@ def test_quantize_argument_errors(vit):
 def test_stream_length_limit(vit):
     # 32-bit byte offsets inside a stream: 2^30 stages of fp32 r1/2 are refused
     _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode, _code(vit), FAKE, 1 << 30, 256, 35, 0, FAKE)
+
+
+# ----------------------------------------------------------------------------- batches (host-side validation)
+
+def _batch_args(vit, frames, codes=None):
+    codes = codes or [_code(vit), vit.make_code(9, (0o561, 0o753))]
+    return vit.codes_array(codes), vit.frames_array(frames)
+
+
+def test_batch_workspace_size_counts_blocks(vit):
+    ca, fa = _batch_args(vit, [(0, 1, 100, 0, 0), (1, 1, 1000, 212, 13), (0, 0, 8, 4000, 200)])
+    t = vit.tunings_array([(64, 35, -1, 1), (256, 45, -1, 2)])
+    # blocks: ceil(100/64) + ceil(1000/256) + ceil(8/64) = 2 + 4 + 1, 40 bytes each after a 256-byte header
+    assert vit.vit_batch_workspace_size(ca, fa, t) == 256 + 7 * 40
+    # untuned: sized for the smallest candidate block (64)
+    assert vit.vit_batch_workspace_size(ca, fa) == 256 + (2 + 16 + 1) * 40
+
+
+def test_batch_argument_errors(vit):
+    E = vit.VIT_EINVAL
+    plan = vit.vit_plan_create()
+    try:
+        ca, fa = _batch_args(vit, [(0, 1, 100, 0, 0)])
+        ok = dict(llr=FAKE, llr_count=212, llr_type=0, out=FAKE, out_bytes=13, ws=0x100000, ws_bytes=1 << 20)
+
+        def call(frames=None, codes=None, tune=None, **kw):
+            a = dict(ok)
+            a.update(kw)
+            c, f = _batch_args(vit, frames or [(0, 1, 100, 0, 0)], codes)
+            vit.vit_decode_batch(plan, c, f, a["llr"], a["llr_count"], a["llr_type"], a["out"], a["out_bytes"],
+                                 tune, a["ws"], a["ws_bytes"], None)
+
+        for bad in ([(2, 1, 100, 0, 0)], [(0, 1, 0, 0, 0)], [(0, 2, 100, 0, 0)], [(0, 1, 100, -1, 0)],
+                    [(0, 1, 100, 1, 0)],                         # LLRs past the end (212 needed from offset 1)
+                    [(0, 1, 100, 0, 1)],                         # output past the end
+                    [(0, 1, 40, 0, 0), (0, 1, 40, 92, 4)]):      # overlapping outputs
+            with pytest.raises(vit.VitError) as ei:
+                call(frames=bad)
+            assert ei.value.status == E, bad
+        for kw in (dict(llr=None), dict(out=None), dict(ws=None), dict(ws=0x100010), dict(llr_type=7),
+                   dict(ws_bytes=100)):
+            with pytest.raises(vit.VitError) as ei:
+                call(**kw)
+            assert ei.value.status == E, kw
+        for t in ((12, 35, -1, 1), (0, 35, -1, 1), (64, -1, -1, 1), (64, 35, 40, 1), (64, 35, -1, 5)):
+            with pytest.raises(vit.VitError) as ei:
+                call(tune=vit.tunings_array([t, t]))
+            assert ei.value.status == E, t
+        with pytest.raises(vit.VitError):
+            vit.vit_decode_batch(plan, vit.codes_array([]), vit.frames_array([(0, 1, 10, 0, 0)]), FAKE, 100, 0,
+                                 FAKE, 10, None, 0x100000, 1 << 20, None)
+    finally:
+        vit.vit_plan_destroy(plan)

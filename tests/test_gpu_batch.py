@@ -1,0 +1,165 @@
+"""Batched decoding (one graph launch, mixed codes and frame lengths) against
+the same frames decoded one by one on the GPU and by the CPU oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import vref
+
+pytestmark = pytest.mark.gpu
+NCPU = max(1, min(16, len(os.sched_getaffinity(0))))
+
+CODES = [(7, (0o171, 0o133)), (7, (0o133, 0o171, 0o165)), (9, (0o561, 0o753)), (5, (0o22, 0o35)),
+         (4, (0o13, 0o15, 0o17, 0o11))]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_09337_amd as vit
+    return torch, vit
+
+
+def make_batch(rng, nframes, code_ids, nmin, nmax, int8=False, ebn0=(1.0, 5.0)):
+    """Frames of random length and code, LLRs packed back to back with gaps,
+    outputs at byte offsets with gaps."""
+    frames, chunks, bits_list = [], [], []
+    llr_off, out_off = 0, 0
+    for f in range(nframes):
+        cid = int(rng.choice(code_ids))
+        k, gens = CODES[cid]
+        n = int(rng.integers(nmin, nmax + 1))
+        term = int(rng.random() < 0.8)
+        bits = synth.info_bits(n, rng)
+        e = float(rng.uniform(*ebn0))
+        llr = synth.awgn_llr(synth.encode(k, gens, bits, bool(term)), e, len(gens), rng)
+        if int8:
+            llr = vref.quantize_i8(llr, 8.0 * synth.noise_sigma(e, len(gens)) ** 2 / 2.0)
+        gap = int(rng.integers(0, 5))
+        chunks.append(np.zeros(gap, dtype=llr.dtype))
+        llr_off += gap
+        frames.append((cid, term, n, llr_off, out_off))
+        chunks.append(llr)
+        llr_off += llr.size
+        out_off += (n + 7) // 8 + int(rng.integers(0, 3))
+        bits_list.append(bits)
+    return frames, np.concatenate(chunks), out_off, bits_list
+
+
+def oracle_frame(fr, llr, shape):
+    cid, term, n, lo, oo = fr
+    k, gens = CODES[cid]
+    N = n + (k - 1 if term else 0)
+    L, v, v1, _ = shape
+    v1 = v // 2 if v1 < 0 else v1
+    sub = llr[lo:lo + N * len(gens)]
+    return synth.pack_bits(vref.decode_blocked(vref.make_code(k, list(gens)), sub, n, L, v1, v - v1, bool(term),
+                                               nthreads=NCPU))
+
+
+def run_batch(dev, batch, frames, llr, out_bytes, code_ids, tune):
+    torch, vit = dev
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    t_llr = torch.from_numpy(llr).cuda()
+    out = torch.full((out_bytes,), 0xAB, dtype=torch.uint8, device="cuda")
+    print(f"[gpu] batch of {len(frames)} frames, tune={tune}", flush=True)
+    batch.decode(codes, frames, t_llr, out, tune=tune)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_frames(got, frames, llr, tunes):
+    for fr in frames:
+        want = oracle_frame(fr, llr, tunes[fr[0]])
+        oo = fr[4]
+        np.testing.assert_array_equal(got[oo:oo + want.size], want, err_msg=f"frame {fr}")
+
+
+TUNE = [(256, 35, -1, 1), (128, 35, 10, 2), (64, 45, -1, 1), (64, 25, -1, 1), (32, 20, -1, 4)]
+
+
+@pytest.mark.parametrize("int8", [False, True])
+def test_batch_mixed_codes_matches_oracle(dev, int8):
+    torch, vit = dev
+    rng = np.random.default_rng(11 + int8)
+    frames, llr, out_bytes, _ = make_batch(rng, 300, [0, 1, 2, 3, 4], 1, 2000, int8=int8)
+    b = vit.Batch()
+    got = run_batch(dev, b, frames, llr, out_bytes, None, TUNE)
+    check_frames(got, frames, llr, TUNE)
+    b.close()
+
+
+def test_batch_equals_frames_alone(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(3)
+    frames, llr, out_bytes, _ = make_batch(rng, 60, [0, 2], 40, 3000)
+    b = vit.Batch()
+    got = run_batch(dev, b, frames, llr, out_bytes, None, TUNE)
+    t_llr = torch.from_numpy(llr).cuda()
+    for fr in frames:
+        cid, term, n, lo, oo = fr
+        k, gens = CODES[cid]
+        N = n + (k - 1 if term else 0)
+        L, v, v1, _ = TUNE[cid]
+        alone = vit.decode(vit.make_code(k, gens), t_llr[lo:lo + N * len(gens)], n, L, v,
+                           v1=None if v1 < 0 else v1, terminated=bool(term))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got[oo:oo + alone.numel()], alone.cpu().numpy())
+    b.close()
+
+
+def test_graph_reuse_with_changing_frames(dev):
+    # same plan and buffers, new frame lists (different counts and lengths):
+    # the graph is reused with a new work-list copy each call
+    torch, vit = dev
+    b = vit.Batch()
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    rng = np.random.default_rng(8)
+    cap_llr, cap_out = 2_000_000, 200_000
+    t_llr = torch.zeros(cap_llr, dtype=torch.float32, device="cuda")
+    out = torch.zeros(cap_out, dtype=torch.uint8, device="cuda")
+    results = []
+    for it in range(4):
+        frames, llr, out_bytes, _ = make_batch(rng, int(rng.integers(20, 120)), [0, 1, 2], 1, 4000)
+        assert llr.size <= cap_llr and out_bytes <= cap_out
+        t_llr[:llr.size].copy_(torch.from_numpy(llr))
+        print(f"[gpu] reuse iteration {it}: {len(frames)} frames", flush=True)
+        b.decode(codes, frames, t_llr, out, tune=TUNE)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        check_frames(got, frames, llr, TUNE)
+        results.append(len(frames))
+    b.close()
+
+
+def test_autotune_then_decode(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(21)
+    frames, llr, out_bytes, _ = make_batch(rng, 200, [0, 1, 2], 40, 6144, int8=True)
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    t_llr = torch.from_numpy(llr).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    b = vit.Batch()
+    chosen = b.autotune(codes, frames, t_llr, out)
+    print("autotuned:", chosen[:3])
+    for t in chosen[:3]:
+        assert t[0] in (64, 128, 256, 512, 1024) and t[3] in (1, 2)
+    out.zero_()
+    b.decode(codes, frames, t_llr, out)  # tune=None: the plan's choices
+    torch.cuda.synchronize()
+    check_frames(out.cpu().numpy(), frames, llr, chosen)
+    b.close()
+
+
+def test_batch_single_and_tiny_frames(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(2)
+    frames, llr, out_bytes, _ = make_batch(rng, 50, [0, 2, 4], 1, 9)
+    b = vit.Batch()
+    got = run_batch(dev, b, frames, llr, out_bytes, None, TUNE)
+    check_frames(got, frames, llr, TUNE)
+    b.close()
