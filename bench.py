@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-frames", type=int, default=8192)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -100,6 +102,103 @@ def cpu_baseline(code_np, llr, n, L, v):
         dt = time.perf_counter() - t0
         res[tag] = (nb / dt / 1e6, nb, dt, th)
     return res
+
+
+BATCH_CODES = ("k7r12", "k7r13", "k9r12")
+
+
+def batched_workload(nframes, seed=0):
+    """Batched configuration: terminated frames, lengths uniform in [40, 6144],
+    code uniform over K=7 r1/2, K=7 r1/3, K=9 r1/2, Eb/N0 uniform in [1, 5] dB."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    frames, chunks, bits, scales = [], [], [], []
+    llr_off = out_off = 0
+    for _ in range(nframes):
+        cid = int(rng.integers(0, len(BATCH_CODES)))
+        k, gens = synth.CODES[BATCH_CODES[cid]]
+        n = int(rng.integers(40, 6145))
+        ebn0 = float(rng.uniform(1.0, 5.0))
+        b = synth.info_bits(n, rng)
+        llr = synth.awgn_llr(synth.encode(k, gens, b, True), ebn0, len(gens), rng)
+        frames.append((cid, 1, n, llr_off, out_off))
+        chunks.append(llr)
+        bits.append(b)
+        # int8 scale: a noiseless symbol (|llr| = 2/sigma^2) maps to amplitude 8
+        scales.append(8.0 * synth.noise_sigma(ebn0, len(gens)) ** 2 / 2.0)
+        llr_off += llr.size
+        out_off += (n + 7) // 8
+    return frames, np.concatenate(chunks), out_off, bits, scales
+
+
+def batch_stages(frames, tunes):
+    """Trellis stages x states processed by a batch (the algorithmic ACS work is 4 lane-ops each)."""
+    import synth
+    work = 0
+    for cid, term, n, _, _ in frames:
+        k, _ = synth.CODES[BATCH_CODES[cid]]
+        L, v, v1, _ = tunes[cid]
+        v1 = v // 2 if v1 < 0 else v1
+        v2 = v - v1
+        N = n + (k - 1 if term else 0)
+        for cs in range(0, n, L):
+            ce = min(cs + L, n)
+            work += (min(N, ce + v2) - max(0, cs - v1)) * (1 << (k - 1))
+    return work
+
+
+def bench_batched(vit, torch, args):
+    import numpy as np
+    import synth
+    frames, llr, out_bytes, bits, scales = batched_workload(args.batched_frames)
+    codes = [vit.make_code(*synth.CODES[c]) for c in BATCH_CODES]
+    llr_d = torch.from_numpy(llr).cuda()
+    q_d = torch.empty(llr.size, dtype=torch.int8, device="cuda")
+    for (cid, term, n, lo, oo), sc in zip(frames, scales):
+        k, gens = synth.CODES[BATCH_CODES[cid]]
+        cnt = (n + (k - 1 if term else 0)) * len(gens)
+        vit.vit_quantize_i8(llr_d.data_ptr() + 4 * lo, cnt, sc, q_d.data_ptr() + lo, None)
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    b = vit.Batch()
+    tunes = b.autotune(codes, frames, q_d, out)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        b.decode(codes, frames, q_d, out, stream=stream)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(steps):
+        b.decode(codes, frames, q_d, out, stream=stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / steps
+    got = out.cpu().numpy()
+    nbits = sum(f[2] for f in frames)
+    err8 = sum(int(np.sum(synth.unpack_bits(got[f[4]:f[4] + (f[2] + 7) // 8], f[2]) != bt))
+               for f, bt in zip(frames, bits))
+    # the same frames and shapes with the fp32 LLRs, for the int8 BER cost
+    out32 = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    b.decode(codes, frames, llr_d, out32, tune=tunes)
+    torch.cuda.synchronize()
+    g32 = out32.cpu().numpy()
+    err32 = sum(int(np.sum(synth.unpack_bits(g32[f[4]:f[4] + (f[2] + 7) // 8], f[2]) != bt))
+                for f, bt in zip(frames, bits))
+    work = 4.0 * batch_stages(frames, tunes)
+    b.close()
+    return {
+        "workload": f"{len(frames)} terminated frames, n uniform in [40, 6144] ({nbits} bits), code uniform over "
+                    f"{'/'.join(BATCH_CODES)}, Eb/N0 uniform in [1, 5] dB, int8 LLRs (noiseless amplitude 8); "
+                    f"one graph launch per step, autotuned shapes",
+        "mbps": round(nbits / (ms * 1e-3) / 1e6, 2),
+        "ms_per_step": round(ms, 4),
+        "valu_frac": round(work / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+        "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
+        "ber_int8": err8 / nbits,
+        "ber_fp32_same_shapes": err32 / nbits,
+    }
 
 
 def main():
@@ -167,6 +266,9 @@ def main():
         cpu = {"value": round(mbps, 3), "unit": "Mbps", "cores": th, "kind": "oracle",
                "sample": f"first {nb} bits of the stream, blocked L={args.L} v={v}, {dt:.2f} s",
                "single_core_mbps": round(res["one"][0], 3)}
+    batched = None if args.no_batched else bench_batched(vit, torch, args)
+    if batched:
+        batched["vs_stream_fp32"] = round(batched["mbps"] / head["mbps"], 3)
     line = {
         "metric": METRIC,
         "value": round(head["mbps"], 2),
@@ -187,6 +289,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ber": ber,
+        "batched": batched,
         "sweep": {str(L): {"mbps": round(s["mbps"], 1), "ms": round(s["ms"], 4),
                            "valu_frac": round(s["tops"] / VALU_PEAK_TOPS, 4)} for L, s in sweep.items()},
         "wall_s_timed": round(head_wall, 4),
