@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-pool", type=int, default=4096)
+    ap.add_argument("--serve-arena-mb", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -198,6 +202,139 @@ def bench_batched(vit, torch, args):
         "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
         "ber_int8": err8 / nbits,
         "ber_fp32_same_shapes": err32 / nbits,
+        "tuning_tuples": [tuple(t) for t in tunes],
+    }
+
+
+def serving_pool(vit, torch, count, seed=7):
+    """Serving configuration's frame pool: lengths lognormal (median 1024,
+    sigma_ln = 1) clipped to [40, 16384], code uniform over the three codes,
+    terminated, Eb/N0 uniform in [1, 5] dB, int8 LLRs quantised on the GPU.
+    Returns (frames [(cid, n, llr_off, out_off)], pinned host region)."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    frames, chunks, scales = [], [], []
+    pos = 0
+    for _ in range(count):
+        cid = int(rng.integers(0, len(BATCH_CODES)))
+        k, gens = synth.CODES[BATCH_CODES[cid]]
+        n = int(np.clip(np.round(rng.lognormal(np.log(1024.0), 1.0)), 40, 16384))
+        ebn0 = float(rng.uniform(1.0, 5.0))
+        llr = synth.awgn_llr(synth.encode(k, gens, synth.info_bits(n, rng), True), ebn0, len(gens), rng)
+        lo = pos
+        oo = (lo + llr.size + 15) // 16 * 16
+        pos = (oo + (n + 7) // 8 + 15) // 16 * 16
+        frames.append((cid, n, lo, oo))
+        chunks.append(llr)
+        scales.append(8.0 * synth.noise_sigma(ebn0, len(gens)) ** 2 / 2.0)
+    f32 = torch.zeros(pos, dtype=torch.float32, device="cuda")
+    q = torch.zeros(pos, dtype=torch.int8, device="cuda")
+    for (cid, n, lo, oo), llr, sc in zip(frames, chunks, scales):
+        f32[lo:lo + llr.size] = torch.from_numpy(llr).cuda()
+        vit.vit_quantize_i8(f32.data_ptr() + 4 * lo, llr.size, sc, q.data_ptr() + lo, None)
+    torch.cuda.synchronize()
+    host = torch.empty(pos, dtype=torch.uint8).pin_memory()
+    host.copy_(q.view(torch.uint8).cpu())
+    return frames, host
+
+
+def bench_serving(vit, torch, args, tunes):
+    """Serving configuration: Poisson arrivals at fractions of the measured
+    capacity, each load point args.serve_seconds long; latency from arrival to
+    the host seeing the frame's last iteration finish."""
+    import numpy as np
+    import synth
+    frames, host = serving_pool(vit, torch, args.serve_pool)
+    codes = [vit.make_code(*synth.CODES[c]) for c in BATCH_CODES]
+    srv = vit.Server(codes, host, tune=tunes, llr_type=vit.VIT_LLR_I8, arena_bytes=args.serve_arena_mb << 20,
+                     max_frames=16384, max_items=1 << 16, max_pending=1 << 24)
+    base = host.data_ptr()
+    P = len(frames)
+    pool = np.zeros(P, dtype=vit.REQUEST_DTYPE)
+    for i, (cid, n, lo, oo) in enumerate(frames):
+        pool[i] = (cid, 1, n, base + lo, base + oo, i, 0)
+    mean_bits = float(np.mean(pool["n"]))
+
+    def requests(first, count, arrivals=None):
+        idx = (first + np.arange(count)) % P
+        r = pool[idx].copy()
+        r["tag"] = first + np.arange(count)
+        if arrivals is not None:
+            r["arrival_ns"] = arrivals
+        return r
+
+    def submit_all(r):
+        off = 0
+        while off < len(r):
+            st, acc = srv.submit(r[off:])
+            off += acc
+            if st == vit.VIT_EBUSY:
+                time.sleep(0.0005)
+
+    try:
+        # capacity: a closed backlog of the pool, repeated
+        srv.stats(reset=True)
+        cap = None
+        for rep in range(3):
+            nreq = P * (2 if rep == 0 else 4)
+            t0 = time.monotonic_ns()
+            submit_all(requests(0, nreq))
+            srv.drain(timeout_ms=120000)
+            srv.poll(1 << 22)
+            st = srv.stats(reset=True)
+            dt = (st["last_done_ns"] - t0) * 1e-9
+            fps = st["completed"] / dt
+            cap = fps if cap is None else max(cap, fps)
+        points = []
+        rng = np.random.default_rng(3)
+        tag = 0
+        for load in (0.25, 0.5, 0.75, 1.0):
+            rate = load * cap
+            dur = args.serve_seconds
+            count = int(rate * dur)
+            gaps = rng.exponential(1.0 / rate, size=count)
+            t0 = time.monotonic_ns() + 5_000_000
+            arr = t0 + (np.cumsum(gaps) * 1e9).astype(np.int64)
+            reqs = requests(tag, count, arr)
+            tag += count
+            i = 0
+            while i < count:
+                now = time.monotonic_ns()
+                j = int(np.searchsorted(arr, now, side="right"))
+                if j > i:
+                    submit_all(reqs[i:j])
+                    i = j
+                srv.poll(1 << 20)
+                if i < count:
+                    wait = (arr[i] - time.monotonic_ns()) * 1e-9
+                    if wait > 2e-4:
+                        time.sleep(wait - 1e-4)
+            srv.drain(timeout_ms=120000)
+            srv.poll(1 << 22)
+            st = srv.stats(reset=True)
+            span = (st["last_done_ns"] - st["first_arrival_ns"]) * 1e-9
+            points.append({
+                "load": load, "offered_fps": round(rate, 1), "frames": st["completed"],
+                "mbps": round(st["bits_completed"] / span / 1e6, 2),
+                "p50_ms": round(st["p50_ns"] * 1e-6, 3), "p99_ms": round(st["p99_ns"] * 1e-6, 3),
+                "max_ms": round(st["max_ns"] * 1e-6, 3), "iterations": st["iterations"],
+                "mean_items_per_iteration": round(st["items_launched"] / max(1, st["iterations"]), 1),
+                "peak_frames_on_device": st["peak_frames_on_device"],
+                "peak_arena_MiB": round(st["peak_arena_bytes"] / 2 ** 20, 2)})
+    finally:
+        srv.close()
+    return {
+        "workload": f"Poisson arrivals at 0.25-1.0 x measured capacity, {args.serve_seconds:g} s per load point; "
+                    f"pool of {P} terminated frames, n lognormal (median 1024, sigma_ln 1) clipped to [40, 16384] "
+                    f"(mean {mean_bits:.0f} bits), code uniform over {'/'.join(BATCH_CODES)}, Eb/N0 uniform in "
+                    f"[1, 5] dB, int8 LLRs in pinned host memory; latency from arrival to completion seen by the "
+                    f"host",
+        "capacity_fps": round(cap, 1),
+        "capacity_mbps": round(cap * mean_bits / 1e6, 2),
+        "arena_MiB": args.serve_arena_mb,
+        "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
+        "points": points,
     }
 
 
@@ -269,6 +406,12 @@ def main():
     batched = None if args.no_batched else bench_batched(vit, torch, args)
     if batched:
         batched["vs_stream_fp32"] = round(batched["mbps"] / head["mbps"], 3)
+    serving = None
+    if not args.no_serving:
+        tunes = batched["tuning_tuples"] if batched else [(256, 5 * synth.CODES[c][0], -1, 1) for c in BATCH_CODES]
+        serving = bench_serving(vit, torch, args, tunes)
+    if batched:
+        batched.pop("tuning_tuples", None)
     line = {
         "metric": METRIC,
         "value": round(head["mbps"], 2),
@@ -290,6 +433,7 @@ def main():
         "cpu_baseline": cpu,
         "ber": ber,
         "batched": batched,
+        "serving": serving,
         "sweep": {str(L): {"mbps": round(s["mbps"], 1), "ms": round(s["ms"], 4),
                            "valu_frac": round(s["tops"] / VALU_PEAK_TOPS, 4)} for L, s in sweep.items()},
         "wall_s_timed": round(head_wall, 4),

@@ -195,6 +195,100 @@ int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, con
                       int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream,
                       vit_tuning *chosen);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop with continuous batching.  Requests are frames whose LLRs
+ * sit in a caller-owned pinned host region; an engine thread owned by the
+ * server admits queued frames while frame slots and device arena memory
+ * allow, and runs iterations of at most max_items blocks (the independent
+ * windows of Sec. III) taken from the admitted frames in arrival order.  A
+ * long frame spreads over several iterations; frames that arrive while the
+ * device is busy join the next one, and two iterations are in flight at once.
+ * Each iteration gathers its new frames' LLRs into the arena, decodes its
+ * blocks with the persistent batch kernels and scatters finished frames'
+ * decoded bytes back into the host region.  A frame's decoded bits are
+ * identical to decoding it alone with vit_decode_ex and its code's
+ * (L, v, v1); only the block is the unit of scheduling, and a block's path
+ * metrics stay on chip.  Latency runs from the request's arrival time to the
+ * moment the engine sees its last iteration finish (CLOCK_MONOTONIC). */
+typedef struct vit_server vit_server;
+
+typedef struct {
+  uint32_t size;             /* sizeof(vit_server_config)                           */
+  int32_t llr_type;          /* VIT_LLR_I8 or VIT_LLR_F32, for every request         */
+  int32_t max_frames;        /* frames admitted to the device at once (slots), >= 1  */
+  int32_t max_items;         /* blocks per iteration, >= 1                           */
+  int32_t max_pending;       /* queued requests beyond which submit says VIT_EBUSY   */
+  int32_t reserved;
+  void *arena;               /* device, 256-aligned: admitted frames' LLRs + output  */
+  size_t arena_bytes;        /* the memory budget that admission respects            */
+  void *workspace;           /* device, 256-aligned, vit_server_workspace_size bytes */
+  size_t workspace_bytes;
+  void *host;                /* pinned host memory (hipHostMalloc) holding every
+                                request's LLRs and decoded bytes                     */
+  size_t host_bytes;
+  void *stream;              /* hipStream_t the server works on (NULL = default)     */
+} vit_server_config;
+
+typedef struct {
+  int32_t code_id;           /* index into the server's codes                        */
+  int32_t terminated;        /* 1: k-1 tail stages follow the n information stages   */
+  int64_t n;                 /* information bits, > 0                                */
+  const void *llr;           /* inside the host region: N*beta LLRs of llr_type      */
+  uint8_t *out;              /* inside the host region: ceil(n/8) bytes, written by
+                                the device before the completion is reported         */
+  uint64_t tag;              /* returned with the completion                         */
+  int64_t arrival_ns;        /* CLOCK_MONOTONIC arrival time; <= 0 = time of submit  */
+} vit_request;
+
+typedef struct {
+  uint64_t tag;
+  int32_t status;            /* VIT_OK, or the device error that stopped the server  */
+  int32_t reserved;
+  int64_t arrival_ns, done_ns;
+} vit_completion;
+
+typedef struct {
+  int64_t submitted, completed, failed, bits_completed;
+  int64_t iterations, items_launched;
+  int64_t pending, frames_on_device, peak_frames_on_device, peak_arena_bytes;
+  int64_t first_arrival_ns, last_done_ns;
+  int64_t p50_ns, p99_ns, max_ns;   /* latency of completed frames */
+} vit_serve_stats;
+
+/* Device workspace bytes for a configuration (two iterations' work lists). */
+int vit_server_workspace_size(const vit_server_config *cfg, size_t *bytes);
+
+/* Create a server for ncodes (1..8) codes with one block shape per code
+ * (tune = NULL: L = 256, v = 5k, v1 = floor(v/2), 1 wave per workgroup).
+ * The arena, workspace and host region stay owned by the caller and must stay
+ * valid until vit_server_destroy returns.  Errors: VIT_EINVAL for bad codes,
+ * shapes, sizes or buffers (not device/pinned memory, misaligned, too small);
+ * VIT_EUNSUPPORTED for shapes without a kernel; VIT_EDEVICE, VIT_ENOMEM. */
+int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *tune, const vit_server_config *cfg,
+                      vit_server **server);
+
+/* Queue requests in order.  *accepted receives how many were taken; on the
+ * first one refused the call stops and returns VIT_EINVAL (bad request, or one
+ * that can never fit the arena), VIT_EBUSY (queue full: retry later) or the
+ * device error that stopped the server.  Thread-safe with poll and stats. */
+int vit_server_submit(vit_server *server, const vit_request *reqs, int32_t count, int32_t *accepted);
+
+/* Move up to max completions (in completion order) into out; *count receives
+ * how many.  A completion with status VIT_OK means its bytes are in place. */
+int vit_server_poll(vit_server *server, vit_completion *out, int32_t max, int32_t *count);
+
+/* Wait until every queued request has completed (timeout_ms < 0: no limit).
+ * VIT_EBUSY on timeout. */
+int vit_server_drain(vit_server *server, int64_t timeout_ms);
+
+/* Counters and latency percentiles of the frames completed since creation or
+ * the last reset (reset != 0 clears them after reading). */
+int vit_server_stats(vit_server *server, vit_serve_stats *stats, int32_t reset);
+
+/* Stop launching, wait for the iterations in flight, free the server.
+ * Requests still queued are dropped without a completion. */
+void vit_server_destroy(vit_server *server);
+
 /* Thread-local description of the last error ("" if none). */
 const char *vit_last_error(void);
 

@@ -8,11 +8,13 @@ PyTorch provides device memory and streams.
 from . import _lib
 from ._lib import (codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy)
+from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
+                   vit_server_poll, vit_server_stats, vit_server_submit, vit_server_workspace_size)
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
 
-__all__ = ["decode", "quantize", "Batch", "codes_array", "frames_array", "tunings_array",
+__all__ = ["decode", "quantize", "Batch", "Server", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
@@ -121,3 +123,93 @@ class Batch:
             stream = torch.cuda.current_stream(llr.device)
         return vit_plan_autotune(self.plan, codes_arr, frames_arr, llr.data_ptr(), llr.numel(), llr_type,
                                  out.data_ptr(), out.numel(), ws, ws_bytes, stream.cuda_stream)
+
+
+# numpy layouts of vit_request and vit_completion (include/vit.h)
+try:
+    import numpy as _np
+
+    REQUEST_DTYPE = _np.dtype([("code_id", "<i4"), ("terminated", "<i4"), ("n", "<i8"), ("llr", "<u8"),
+                               ("out", "<u8"), ("tag", "<u8"), ("arrival_ns", "<i8")])
+    COMPLETION_DTYPE = _np.dtype([("tag", "<u8"), ("status", "<i4"), ("reserved", "<i4"), ("arrival_ns", "<i8"),
+                                  ("done_ns", "<i8")])
+except ImportError:  # pragma: no cover
+    REQUEST_DTYPE = COMPLETION_DTYPE = None
+
+
+class Server:
+    """The serving loop of include/vit.h (vit_server_*), with its device arena
+    and workspace held as torch tensors.
+
+    codes: list of vit_code; tune: one (L, v, v1, waves_per_block) per code or
+    None; host: a pinned uint8 torch tensor holding every request's LLRs and
+    output bytes (requests address it by byte offset, see `requests`)."""
+
+    def __init__(self, codes, host, *, tune=None, llr_type=VIT_LLR_I8, arena_bytes=64 << 20, max_frames=4096,
+                 max_items=65536, max_pending=1 << 20, device="cuda", stream=None):
+        import torch
+
+        if not host.is_pinned() or host.dtype != torch.uint8:
+            raise ValueError("host must be a pinned uint8 tensor")
+        self.host = host
+        self.codes = list(codes)
+        cfg = vit_server_config()
+        cfg.size = C_sizeof(vit_server_config)
+        cfg.llr_type = llr_type
+        cfg.max_frames = max_frames
+        cfg.max_items = max_items
+        cfg.max_pending = max_pending
+        ws_bytes = vit_server_workspace_size(cfg)
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
+        self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=device)
+        cfg.arena = (self.arena.data_ptr() + 255) // 256 * 256
+        cfg.arena_bytes = arena_bytes
+        cfg.workspace = (self.ws.data_ptr() + 255) // 256 * 256
+        cfg.workspace_bytes = ws_bytes
+        cfg.host = host.data_ptr()
+        cfg.host_bytes = host.numel()
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        cfg.stream = self.stream.cuda_stream
+        self.cfg = cfg
+        self.server = vit_server_create(codes_array(self.codes), tunings_array(tune) if tune is not None else None,
+                                        cfg)
+        self.host_base = host.data_ptr()
+
+    def requests(self, count):
+        """A zeroed request array of `count` records."""
+        return _np.zeros(count, dtype=REQUEST_DTYPE)
+
+    def submit(self, reqs):
+        """Queue a REQUEST_DTYPE array (llr/out as absolute host addresses).
+        Returns (status, accepted): VIT_OK, or VIT_EBUSY with a partial count."""
+        reqs = _np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        if len(reqs) == 0:
+            return VIT_OK, 0
+        return vit_server_submit(self.server, reqs.ctypes.data, len(reqs))
+
+    def poll(self, max_count=65536):
+        buf = _np.empty(max_count, dtype=COMPLETION_DTYPE)
+        n = vit_server_poll(self.server, buf.ctypes.data, max_count)
+        return buf[:n]
+
+    def drain(self, timeout_ms=-1):
+        return vit_server_drain(self.server, timeout_ms)
+
+    def stats(self, reset=False):
+        return vit_server_stats(self.server, reset)
+
+    def close(self):
+        if getattr(self, "server", None) is not None:
+            vit_server_destroy(self.server)
+            self.server = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def C_sizeof(t):
+    import ctypes
+    return ctypes.sizeof(t)

@@ -50,6 +50,31 @@ class vit_tuning(C.Structure):
     _fields_ = [("L", C.c_int32), ("v", C.c_int32), ("v1", C.c_int32), ("waves_per_block", C.c_int32)]
 
 
+class vit_server_config(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("max_frames", C.c_int32),
+                ("max_items", C.c_int32), ("max_pending", C.c_int32), ("reserved", C.c_int32),
+                ("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("host", C.c_void_p), ("host_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class vit_request(C.Structure):
+    _fields_ = [("code_id", C.c_int32), ("terminated", C.c_int32), ("n", C.c_int64), ("llr", C.c_void_p),
+                ("out", C.c_void_p), ("tag", C.c_uint64), ("arrival_ns", C.c_int64)]
+
+
+class vit_completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32), ("arrival_ns", C.c_int64),
+                ("done_ns", C.c_int64)]
+
+
+class vit_serve_stats(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in (
+        "submitted", "completed", "failed", "bits_completed", "iterations", "items_launched", "pending",
+        "frames_on_device", "peak_frames_on_device", "peak_arena_bytes", "first_arrival_ns", "last_done_ns",
+        "p50_ns", "p99_ns", "max_ns")]
+
+
 class VitError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -89,6 +114,21 @@ lib.vit_decode_batch.restype = C.c_int
 lib.vit_plan_autotune.argtypes = [C.c_void_p, _PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P,
                                   C.c_int64, _P, C.c_size_t, _P, _PT]
 lib.vit_plan_autotune.restype = C.c_int
+_PS = C.POINTER(vit_server_config)
+lib.vit_server_workspace_size.argtypes = [_PS, C.POINTER(C.c_size_t)]
+lib.vit_server_workspace_size.restype = C.c_int
+lib.vit_server_create.argtypes = [_PC, C.c_int32, _PT, _PS, C.POINTER(C.c_void_p)]
+lib.vit_server_create.restype = C.c_int
+lib.vit_server_submit.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(C.c_int32)]
+lib.vit_server_submit.restype = C.c_int
+lib.vit_server_poll.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(C.c_int32)]
+lib.vit_server_poll.restype = C.c_int
+lib.vit_server_drain.argtypes = [C.c_void_p, C.c_int64]
+lib.vit_server_drain.restype = C.c_int
+lib.vit_server_stats.argtypes = [C.c_void_p, C.POINTER(vit_serve_stats), C.c_int32]
+lib.vit_server_stats.restype = C.c_int
+lib.vit_server_destroy.argtypes = [C.c_void_p]
+lib.vit_server_destroy.restype = None
 lib.vit_last_error.argtypes = []
 lib.vit_last_error.restype = C.c_char_p
 lib.vit_abi_version.argtypes = []
@@ -194,3 +234,45 @@ def vit_plan_autotune(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type,
     _check(lib.vit_plan_autotune(plan, codes_arr, len(codes_arr), frames_arr, len(frames_arr), llr_ptr, llr_count,
                                  llr_type, out_ptr, out_bytes, ws_ptr, ws_bytes, stream, chosen))
     return [(t.L, t.v, t.v1, t.waves_per_block) for t in chosen]
+
+
+def vit_server_workspace_size(cfg):
+    b = C.c_size_t()
+    _check(lib.vit_server_workspace_size(C.byref(cfg), C.byref(b)))
+    return b.value
+
+
+def vit_server_create(codes_arr, tune_arr, cfg):
+    p = C.c_void_p()
+    _check(lib.vit_server_create(codes_arr, len(codes_arr), tune_arr, C.byref(cfg), C.byref(p)))
+    return p
+
+
+def vit_server_submit(server, reqs_ptr, count):
+    """reqs_ptr: address of `count` packed vit_request records.  Returns
+    (status, accepted); VIT_EBUSY is returned, not raised."""
+    acc = C.c_int32()
+    st = lib.vit_server_submit(server, reqs_ptr, count, C.byref(acc))
+    if st not in (VIT_OK, VIT_EBUSY):
+        raise VitError(st, vit_last_error())
+    return st, acc.value
+
+
+def vit_server_poll(server, out_ptr, max_count):
+    n = C.c_int32()
+    _check(lib.vit_server_poll(server, out_ptr, max_count, C.byref(n)))
+    return n.value
+
+
+def vit_server_drain(server, timeout_ms=-1):
+    return _check(lib.vit_server_drain(server, timeout_ms))
+
+
+def vit_server_stats(server, reset=False):
+    st = vit_serve_stats()
+    _check(lib.vit_server_stats(server, C.byref(st), 1 if reset else 0))
+    return {name: getattr(st, name) for name, _ in vit_serve_stats._fields_}
+
+
+def vit_server_destroy(server):
+    lib.vit_server_destroy(server)

@@ -1,0 +1,41 @@
+// vit_copy.hip -- gather/scatter of byte ranges listed in device memory, used
+// by the serving loop to move the LLRs of newly admitted frames from pinned
+// host memory into the device arena, and decoded bytes back, in one launch
+// per iteration however many frames it holds.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vit_internal.h"
+
+namespace vit {
+namespace {
+
+// One workgroup per range (grid-strided): 16-byte words when source,
+// destination and length allow, bytes otherwise.
+__global__ __launch_bounds__(256) void copy_list_kernel(const CopyRange *__restrict__ r, int32_t count) {
+  for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const uint8_t *src = r[i].src;
+    uint8_t *dst = r[i].dst;
+    const int64_t bytes = r[i].bytes;
+    int64_t done = 0;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
+      const int64_t nw = bytes >> 4;
+      const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+      uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+      for (int64_t j = threadIdx.x; j < nw; j += blockDim.x) d4[j] = s4[j];
+      done = nw << 4;
+    }
+    for (int64_t j = done + threadIdx.x; j < bytes; j += blockDim.x) dst[j] = src[j];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_copy_list(const CopyRange *ranges, int32_t count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  const int grid = count < 2048 ? count : 2048;
+  hipLaunchKernelGGL(copy_list_kernel, dim3(grid), dim3(256), 0, stream, ranges, count);
+  return hipGetLastError();
+}
+
+}  // namespace vit

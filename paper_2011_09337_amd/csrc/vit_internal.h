@@ -82,6 +82,17 @@ int api_fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 
 int api_fail_hip(hipError_t e, const char *what);
 int api_check_code(const vit_code *c);
 
+// A byte range to copy on the device (either side may be pinned host memory
+// mapped for the device).  32 bytes, the layout the copy kernel reads.
+struct CopyRange {
+  const uint8_t *src;
+  uint8_t *dst;
+  int64_t bytes;
+  int64_t pad;
+};
+// Copy `count` ranges listed in device memory (vit_copy.hip).
+hipError_t launch_copy_list(const CopyRange *ranges, int32_t count, hipStream_t stream);
+
 // Launch the int8 quantiser (vit_quantize.hip) on `stream`.
 hipError_t launch_quantize(const float *llr, int64_t count, float scale, int8_t *q, hipStream_t stream);
 

@@ -1,0 +1,539 @@
+// vit_server.cpp -- the serving loop: continuous batching of decode requests.
+//
+// Requests (one frame each, LLRs in a pinned host region) are queued by
+// vit_server_submit.  An engine thread owned by the server runs iterations:
+// each admits queued frames while slots and device arena memory allow (the
+// scheduling lives in vit_server_core.h), then issues, on the server's
+// stream, one host-to-device copy of the iteration's work list, one gather of
+// the new frames' LLRs from the host region into the arena, one persistent
+// batch kernel per code over the iteration's blocks, one scatter of the
+// finished frames' decoded bytes into the host region, and an event.  Two
+// iterations are in flight at once, so requests that arrive while the device
+// is busy join the next iteration and their work overlaps the running one.
+// A frame completes when the host sees its last iteration's event; its
+// latency runs from its arrival time to that moment (CLOCK_MONOTONIC).
+#include <hip/hip_runtime.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "vit.h"
+#include "vit_internal.h"
+#include "vit_server_core.h"
+
+namespace {
+
+using vit::api_fail;
+using vit::kHeaderBytes;
+using vit::kMaxCodes;
+
+constexpr int kInflight = 2;
+
+int64_t mono_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Per iteration slot: header | items | ingest ranges | egress ranges.
+size_t slot_bytes(int32_t max_frames, int32_t max_items) {
+  return round256(kHeaderBytes + (size_t)max_items * sizeof(vit::WorkItem) +
+                  2 * (size_t)max_frames * sizeof(vit::CopyRange));
+}
+
+int check_config(const vit_server_config *cfg) {
+  if (!cfg) return api_fail(VIT_EINVAL, "config is NULL");
+  if (cfg->size != sizeof(vit_server_config))
+    return api_fail(VIT_EINVAL, "config size %u, expected %zu", cfg->size, sizeof(vit_server_config));
+  if (cfg->llr_type != VIT_LLR_F32 && cfg->llr_type != VIT_LLR_I8)
+    return api_fail(VIT_EINVAL, "unknown llr_type %d", cfg->llr_type);
+  if (cfg->max_frames < 1 || cfg->max_frames > (1 << 20))
+    return api_fail(VIT_EINVAL, "max_frames = %d outside [1, 2^20]", cfg->max_frames);
+  if (cfg->max_items < 1 || cfg->max_items > (1 << 24))
+    return api_fail(VIT_EINVAL, "max_items = %d outside [1, 2^24]", cfg->max_items);
+  if (cfg->max_pending < 1) return api_fail(VIT_EINVAL, "max_pending = %d must be >= 1", cfg->max_pending);
+  return VIT_OK;
+}
+
+bool in_range(const uint8_t *base, size_t size, const void *p, int64_t bytes) {
+  const uint8_t *q = (const uint8_t *)p;
+  return q >= base && bytes >= 0 && (size_t)(q - base) <= size && (size_t)bytes <= size - (size_t)(q - base);
+}
+
+// Both ends of [p, p + bytes) must be memory of the given type.
+int check_memory(const void *p, size_t bytes, hipMemoryType want, const char *what) {
+  hipPointerAttribute_t a0, a1;
+  hipError_t e = hipPointerGetAttributes(&a0, p);
+  if (e != hipSuccess) return api_fail(VIT_EINVAL, "%s: not HIP memory (%s)", what, hipGetErrorString(e));
+  e = hipPointerGetAttributes(&a1, (const uint8_t *)p + bytes - 1);
+  if (e != hipSuccess) return api_fail(VIT_EINVAL, "%s: its end is not HIP memory (%s)", what, hipGetErrorString(e));
+  if (a0.type != want || a1.type != want)
+    return api_fail(VIT_EINVAL, "%s: must be %s memory", what, want == hipMemoryTypeHost ? "pinned host" : "device");
+  return VIT_OK;
+}
+
+}  // namespace
+
+struct vit_server {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  int llr_type = VIT_LLR_I8;
+  int elem = 1;
+  int ncodes = 0;
+  vit_code codes[kMaxCodes];
+  vit_tuning shape[kMaxCodes];
+  vit::BatchLaunch bl[kMaxCodes];
+  uint8_t *arena = nullptr;
+  size_t arena_bytes = 0;
+  uint8_t *ws = nullptr;
+  size_t slot_bytes = 0;
+  uint8_t *host = nullptr;      // host region (host address)
+  uint8_t *host_dev = nullptr;  // the same region as the device addresses it
+  size_t host_bytes = 0;
+  int32_t max_frames = 0, max_items = 0, max_pending = 0;
+
+  void *staging[kInflight] = {nullptr, nullptr};
+  hipEvent_t ev[kInflight] = {nullptr, nullptr};
+
+  std::mutex mu;
+  std::condition_variable cv;      // wakes the engine: submit, stop
+  std::condition_variable idle_cv; // wakes drain: progress
+  vit::serve::Core *core = nullptr;
+  vit::serve::Iteration iters[kInflight];  // reused, so their buffers keep their capacity
+  std::deque<int> inflight;                // slots of the iterations on the device, oldest first
+  int next_slot = 0;
+  std::deque<vit_completion> done;
+  std::vector<int64_t> lat;
+  int64_t submitted = 0, completed = 0, failed_frames = 0, bits_completed = 0, iterations = 0,
+          items_launched = 0, peak_arena = 0, peak_frames = 0, first_arrival = 0, last_done = 0;
+  int status = VIT_OK;
+  std::string fail_msg;
+  bool stop = false;
+  std::thread engine;
+};
+
+namespace {
+
+// Write the iteration's work list into pinned staging and issue its work.
+// Called by the engine thread without the lock (the iteration is private).
+int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, std::string *msg) {
+  uint8_t *stg = (uint8_t *)s->staging[slot];
+  uint8_t *wsd = s->ws + (size_t)slot * s->slot_bytes;
+  int32_t *header = (int32_t *)stg;
+  memset(header, 0, kHeaderBytes);
+  vit::WorkItem *wi = (vit::WorkItem *)(stg + kHeaderBytes);
+  int32_t count[kMaxCodes] = {0};
+  for (const auto &b : it.items) ++count[b.code];
+  int32_t off = 0;
+  for (int c = 0; c < s->ncodes; ++c) {
+    header[kMaxCodes + c] = count[c];
+    header[2 * kMaxCodes + c] = off;
+    off += count[c];
+  }
+  for (size_t i = 0; i < it.items.size(); ++i) {  // items arrive grouped by code, longest first
+    const auto &b = it.items[i];
+    vit::WorkItem &w = wi[i];
+    w.llr_off = b.llr_off;
+    w.out_off = b.out_off;
+    w.s = b.s;
+    w.e = b.e;
+    w.cs = b.cs;
+    w.ce = b.ce;
+    w.flags = b.flags;
+    w.cost = b.cost;
+  }
+  const size_t items_end = kHeaderBytes + it.items.size() * sizeof(vit::WorkItem);
+  vit::CopyRange *cr = (vit::CopyRange *)(stg + items_end);
+  for (size_t i = 0; i < it.ingest.size(); ++i)
+    cr[i] = {s->host_dev + it.ingest[i].src, s->arena + it.ingest[i].dst, it.ingest[i].bytes, 0};
+  vit::CopyRange *er = cr + it.ingest.size();
+  for (size_t i = 0; i < it.egress.size(); ++i)
+    er[i] = {s->arena + it.egress[i].src, s->host_dev + it.egress[i].dst, it.egress[i].bytes, 0};
+  const size_t used = items_end + (it.ingest.size() + it.egress.size()) * sizeof(vit::CopyRange);
+
+  hipError_t e = hipMemcpyAsync(wsd, stg, used, hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return *msg = std::string("hipMemcpyAsync: ") + hipGetErrorString(e), VIT_EDEVICE;
+  const vit::CopyRange *dcr = (const vit::CopyRange *)(wsd + items_end);
+  e = vit::launch_copy_list(dcr, (int32_t)it.ingest.size(), s->stream);
+  if (e != hipSuccess) return *msg = std::string("ingest: ") + hipGetErrorString(e), VIT_EDEVICE;
+  for (int c = 0; c < s->ncodes; ++c) {
+    if (!count[c]) continue;
+    vit::BatchArgs a;
+    a.llr = s->arena;
+    a.out = s->arena;
+    a.header = (int32_t *)wsd;
+    a.items = (const vit::WorkItem *)(wsd + kHeaderBytes);
+    a.code_index = c;
+    for (int b = 0; b < 4; ++b) a.gen[b] = b < s->codes[c].beta ? s->codes[c].gen[b] : 0u;
+    int words = s->bl[c].lds_words_per_wave;
+    void *kargs[] = {&a, &words};
+    const unsigned wpb = s->bl[c].block / 64;
+    unsigned grid = (unsigned)((count[c] + wpb - 1) / wpb);
+    if (grid > s->bl[c].grid) grid = s->bl[c].grid;
+    e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
+    if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
+  }
+  e = vit::launch_copy_list(dcr + it.ingest.size(), (int32_t)it.egress.size(), s->stream);
+  if (e != hipSuccess) return *msg = std::string("egress: ") + hipGetErrorString(e), VIT_EDEVICE;
+  e = hipEventRecord(s->ev[slot], s->stream);
+  if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
+  return VIT_OK;
+}
+
+void fail_locked(vit_server *s, int status, const std::string &msg) {
+  if (s->status == VIT_OK) {
+    s->status = status;
+    s->fail_msg = msg;
+  }
+}
+
+void engine_main(vit_server *s) {
+  (void)hipSetDevice(s->dev);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    // retire finished iterations, oldest first
+    while (!s->inflight.empty()) {
+      const hipError_t q = hipEventQuery(s->ev[s->inflight.front()]);
+      if (q == hipErrorNotReady) break;
+      const int64_t now = mono_ns();
+      const int st = q == hipSuccess ? VIT_OK : VIT_EDEVICE;
+      if (st != VIT_OK) fail_locked(s, st, std::string("iteration failed: ") + hipGetErrorString(q));
+      vit::serve::Iteration &it = s->iters[s->inflight.front()];
+      for (const auto &f : it.finishing) {
+        vit_completion c;
+        c.tag = f.tag;
+        c.status = st;
+        c.reserved = 0;
+        c.arrival_ns = f.arrival_ns;
+        c.done_ns = now;
+        s->done.push_back(c);
+        if (st == VIT_OK) {
+          ++s->completed;
+          s->bits_completed += f.n;
+          s->lat.push_back(now - f.arrival_ns);
+        } else {
+          ++s->failed_frames;
+        }
+        s->last_done = now;
+      }
+      s->core->retire(it);
+      s->inflight.pop_front();
+      s->idle_cv.notify_all();
+    }
+    if (s->status != VIT_OK && s->inflight.empty() && s->core->has_work()) {
+      // after a device error nothing more is launched: queued and admitted
+      // frames complete with the error
+      const int64_t now = mono_ns();
+      s->core->fail_all([&](const vit::serve::Frame &f) {
+        s->done.push_back({f.tag, s->status, 0, f.arrival_ns, now});
+        ++s->failed_frames;
+      });
+      s->idle_cv.notify_all();
+    }
+    if (s->stop && s->inflight.empty()) break;
+    if (s->status == VIT_OK && !s->stop && (int)s->inflight.size() < kInflight && s->core->has_work()) {
+      const int slot = s->next_slot;
+      vit::serve::Iteration &it = s->iters[slot];
+      if (s->core->next_iteration(&it)) {
+        s->next_slot = (slot + 1) % kInflight;
+        s->peak_arena = std::max(s->peak_arena, s->core->arena_in_use());
+        s->peak_frames = std::max(s->peak_frames, s->core->frames_on_device());
+        ++s->iterations;
+        s->items_launched += (int64_t)it.items.size();
+        s->inflight.push_back(slot);
+        lk.unlock();
+        std::string msg;
+        const int st = launch_iteration(s, it, slot, &msg);
+        lk.lock();
+        if (st != VIT_OK) {
+          fail_locked(s, st, msg);
+          // the iteration's event was not recorded: its frames fail now
+          for (const auto &f : it.finishing) {
+            s->done.push_back({f.tag, st, 0, f.arrival_ns, mono_ns()});
+            ++s->failed_frames;
+          }
+          s->core->retire(it);
+          s->inflight.pop_back();
+          s->idle_cv.notify_all();
+        }
+        continue;
+      }
+    }
+    // nothing to launch: wait for a submit, or poll the running iteration
+    if (!s->inflight.empty()) s->cv.wait_for(lk, std::chrono::microseconds(20));
+    else s->cv.wait_for(lk, std::chrono::milliseconds(2));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vit_server_workspace_size(const vit_server_config *cfg, size_t *bytes) {
+  vit::api_clear_error();
+  int st = check_config(cfg);
+  if (st) return st;
+  if (!bytes) return api_fail(VIT_EINVAL, "bytes is NULL");
+  *bytes = kInflight * slot_bytes(cfg->max_frames, cfg->max_items);
+  return VIT_OK;
+}
+
+int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *tune, const vit_server_config *cfg,
+                      vit_server **out) {
+  vit::api_clear_error();
+  if (!out) return api_fail(VIT_EINVAL, "server is NULL");
+  *out = nullptr;
+  if (!codes || ncodes < 1 || ncodes > kMaxCodes) return api_fail(VIT_EINVAL, "ncodes = %d outside [1, 8]", ncodes);
+  int st;
+  for (int c = 0; c < ncodes; ++c)
+    if ((st = vit::api_check_code(&codes[c]))) return st;
+  if ((st = check_config(cfg))) return st;
+  vit_tuning shape[kMaxCodes];
+  for (int c = 0; c < ncodes; ++c) {
+    if (tune) {
+      shape[c] = tune[c];
+    } else {
+      shape[c].L = 256;
+      shape[c].v = 5 * codes[c].k;
+      shape[c].v1 = -1;
+      shape[c].waves_per_block = 1;
+    }
+    const vit_tuning &t = shape[c];
+    if (t.L <= 0 || t.L % 8 != 0) return api_fail(VIT_EINVAL, "code %d: L = %d must be a positive multiple of 8", c, t.L);
+    if (t.v < 0 || t.v1 < -1 || t.v1 > t.v) return api_fail(VIT_EINVAL, "code %d: bad overlap (v %d, v1 %d)", c, t.v, t.v1);
+    if (t.waves_per_block < 1 || t.waves_per_block > 4)
+      return api_fail(VIT_EINVAL, "code %d: waves_per_block = %d outside [1, 4]", c, t.waves_per_block);
+    if (cfg->llr_type == VIT_LLR_I8 && ((int64_t)t.L + t.v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
+      return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
+  }
+  if (!cfg->arena || !cfg->workspace || !cfg->host) return api_fail(VIT_EINVAL, "NULL arena, workspace or host region");
+  if ((((uintptr_t)cfg->arena | (uintptr_t)cfg->workspace) & 255u) != 0)
+    return api_fail(VIT_EINVAL, "arena and workspace must be 256-byte aligned");
+  const size_t need_ws = kInflight * slot_bytes(cfg->max_frames, cfg->max_items);
+  if (cfg->workspace_bytes < need_ws)
+    return api_fail(VIT_EINVAL, "workspace of %zu bytes, %zu needed", cfg->workspace_bytes, need_ws);
+  if (cfg->arena_bytes < 256 || cfg->host_bytes < 1) return api_fail(VIT_EINVAL, "empty arena or host region");
+
+  // from here on the device is used
+  if ((st = check_memory(cfg->arena, cfg->arena_bytes, hipMemoryTypeDevice, "arena"))) return st;
+  if ((st = check_memory(cfg->workspace, cfg->workspace_bytes, hipMemoryTypeDevice, "workspace"))) return st;
+  if ((st = check_memory(cfg->host, cfg->host_bytes, hipMemoryTypeHost, "host region"))) return st;
+
+  vit_server *s = new (std::nothrow) vit_server();
+  if (!s) return api_fail(VIT_ENOMEM, "server allocation failed");
+  auto bail = [&](int status) {
+    for (int i = 0; i < kInflight; ++i) {
+      if (s->staging[i]) (void)hipHostFree(s->staging[i]);
+      if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+    }
+    delete s->core;
+    delete s;
+    return status;
+  };
+  hipError_t e = hipGetDevice(&s->dev);
+  if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipGetDevice"));
+  void *hd = nullptr;
+  e = hipHostGetDevicePointer(&hd, cfg->host, 0);
+  if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostGetDevicePointer"));
+  s->stream = (hipStream_t)cfg->stream;
+  s->llr_type = cfg->llr_type;
+  s->elem = cfg->llr_type == VIT_LLR_I8 ? 1 : 4;
+  s->ncodes = ncodes;
+  s->arena = (uint8_t *)cfg->arena;
+  s->arena_bytes = cfg->arena_bytes;
+  s->ws = (uint8_t *)cfg->workspace;
+  s->slot_bytes = slot_bytes(cfg->max_frames, cfg->max_items);
+  s->host = (uint8_t *)cfg->host;
+  s->host_dev = (uint8_t *)hd;
+  s->host_bytes = cfg->host_bytes;
+  s->max_frames = cfg->max_frames;
+  s->max_items = cfg->max_items;
+  s->max_pending = cfg->max_pending;
+  std::vector<vit::serve::CodeShape> shapes;
+  for (int c = 0; c < ncodes; ++c) {
+    s->codes[c] = codes[c];
+    s->shape[c] = shape[c];
+    int unsupported = 0;
+    const char *why = "";
+    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type == VIT_LLR_I8,
+                               (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &s->bl[c], &unsupported,
+                               &why);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "batch launch planning"));
+    if (unsupported) return bail(api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why));
+    const int64_t v1 = shape[c].v1 < 0 ? shape[c].v / 2 : shape[c].v1;
+    shapes.push_back({codes[c].k, codes[c].beta, shape[c].L, v1, shape[c].v - v1});
+  }
+  for (int i = 0; i < kInflight; ++i) {
+    e = hipHostMalloc(&s->staging[i], s->slot_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostMalloc"));
+    e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
+  }
+  s->core = new (std::nothrow) vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames,
+                                                cfg->max_items);
+  if (!s->core) return bail(api_fail(VIT_ENOMEM, "core allocation failed"));
+  try {
+    s->engine = std::thread(engine_main, s);
+  } catch (...) {
+    return bail(api_fail(VIT_ENOMEM, "could not start the engine thread"));
+  }
+  *out = s;
+  return VIT_OK;
+}
+
+int vit_server_submit(vit_server *s, const vit_request *reqs, int32_t count, int32_t *accepted) {
+  vit::api_clear_error();
+  if (accepted) *accepted = 0;
+  if (!s) return api_fail(VIT_EINVAL, "server is NULL");
+  if (count < 0 || (count > 0 && !reqs)) return api_fail(VIT_EINVAL, "bad request array");
+  const int64_t now = mono_ns();
+  int st = VIT_OK;
+  int32_t took = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->status != VIT_OK) return api_fail(s->status, "server failed: %s", s->fail_msg.c_str());
+    for (; took < count; ++took) {
+      const vit_request &r = reqs[took];
+      if (r.code_id < 0 || r.code_id >= s->ncodes) {
+        st = api_fail(VIT_EINVAL, "request %d: code_id %d", took, r.code_id);
+        break;
+      }
+      if (r.n <= 0 || (r.terminated != 0 && r.terminated != 1)) {
+        st = api_fail(VIT_EINVAL, "request %d: n = %lld, terminated = %d", took, (long long)r.n, r.terminated);
+        break;
+      }
+      const vit_code &c = s->codes[r.code_id];
+      const int64_t N = r.n + (r.terminated ? c.k - 1 : 0);
+      if (N * c.beta * s->elem >= ((int64_t)1 << 31)) {
+        st = api_fail(VIT_EUNSUPPORTED, "request %d: frame too long", took);
+        break;
+      }
+      vit::serve::Frame f;
+      f.tag = r.tag;
+      f.code = r.code_id;
+      f.terminated = r.terminated;
+      f.n = r.n;
+      f.N = N;
+      f.llr_bytes = N * c.beta * s->elem;
+      if (!in_range(s->host, s->host_bytes, r.llr, f.llr_bytes) ||
+          !in_range(s->host, s->host_bytes, r.out, (r.n + 7) / 8)) {
+        st = api_fail(VIT_EINVAL, "request %d: LLRs or output outside the host region", took);
+        break;
+      }
+      f.llr_src = (const uint8_t *)r.llr - s->host;
+      f.out_dst = r.out - s->host;
+      f.arrival_ns = r.arrival_ns > 0 ? r.arrival_ns : now;
+      if (!s->core->fits_ever(f)) {
+        st = api_fail(VIT_EINVAL, "request %d: needs %lld arena bytes, more than the arena", took,
+                      (long long)s->core->arena_need(f));
+        break;
+      }
+      if ((int64_t)s->core->pending() >= s->max_pending) {
+        st = api_fail(VIT_EBUSY, "request queue full (%d pending)", s->max_pending);
+        break;
+      }
+      s->core->submit(f);
+      ++s->submitted;
+      if (s->first_arrival == 0 || f.arrival_ns < s->first_arrival) s->first_arrival = f.arrival_ns;
+    }
+  }
+  if (took) s->cv.notify_one();
+  if (accepted) *accepted = took;
+  return st;
+}
+
+int vit_server_poll(vit_server *s, vit_completion *out, int32_t max, int32_t *count) {
+  vit::api_clear_error();
+  if (count) *count = 0;
+  if (!s || !count || max < 0 || (max > 0 && !out)) return api_fail(VIT_EINVAL, "bad poll arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t n = 0;
+  while (n < max && !s->done.empty()) {
+    out[n++] = s->done.front();
+    s->done.pop_front();
+  }
+  *count = n;
+  return VIT_OK;
+}
+
+int vit_server_drain(vit_server *s, int64_t timeout_ms) {
+  vit::api_clear_error();
+  if (!s) return api_fail(VIT_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+  while (s->core->has_work() || !s->inflight.empty()) {
+    if (timeout_ms >= 0 && s->idle_cv.wait_until(lk, deadline) == std::cv_status::timeout &&
+        (s->core->has_work() || !s->inflight.empty()))
+      return api_fail(VIT_EBUSY, "work still queued after %lld ms", (long long)timeout_ms);
+    if (timeout_ms < 0) s->idle_cv.wait(lk);
+  }
+  if (s->status != VIT_OK) return api_fail(s->status, "server failed: %s", s->fail_msg.c_str());
+  return VIT_OK;
+}
+
+int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
+  vit::api_clear_error();
+  if (!s || !st) return api_fail(VIT_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  memset(st, 0, sizeof(*st));
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->failed = s->failed_frames;
+  st->bits_completed = s->bits_completed;
+  st->iterations = s->iterations;
+  st->items_launched = s->items_launched;
+  st->pending = (int64_t)s->core->pending();
+  st->frames_on_device = s->core->frames_on_device();
+  st->peak_frames_on_device = s->peak_frames;
+  st->peak_arena_bytes = s->peak_arena;
+  st->first_arrival_ns = s->first_arrival;
+  st->last_done_ns = s->last_done;
+  if (!s->lat.empty()) {
+    std::vector<int64_t> v(s->lat);
+    auto pct = [&](double p) {
+      size_t i = (size_t)(p * (double)(v.size() - 1) + 0.5);
+      std::nth_element(v.begin(), v.begin() + (std::ptrdiff_t)i, v.end());
+      return v[i];
+    };
+    st->p50_ns = pct(0.50);
+    st->p99_ns = pct(0.99);
+    st->max_ns = *std::max_element(v.begin(), v.end());
+  }
+  if (reset) {
+    s->lat.clear();
+    s->submitted = s->completed = s->failed_frames = s->bits_completed = 0;
+    s->iterations = s->items_launched = 0;
+    s->peak_arena = s->peak_frames = 0;
+    s->first_arrival = s->last_done = 0;
+  }
+  return VIT_OK;
+}
+
+void vit_server_destroy(vit_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->engine.joinable()) s->engine.join();
+  for (int i = 0; i < kInflight; ++i) {
+    if (s->staging[i]) (void)hipHostFree(s->staging[i]);
+    if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+  }
+  delete s->core;
+  delete s;
+}
+
+}  // extern "C"

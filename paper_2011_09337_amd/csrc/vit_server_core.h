@@ -1,0 +1,274 @@
+// vit_server_core.h -- host-side scheduling of the serving loop, free of HIP
+// so that it can be driven by a fake device in CPU tests.
+//
+// A request is one terminated or open frame.  The core keeps three sets:
+//   pending  -- submitted, waiting for a slot and arena memory (FIFO);
+//   active   -- admitted: its LLRs and decoded bytes have arena space on the
+//               device; some of its blocks are not yet launched;
+//   launched -- every block launched; finishes when its last iteration does.
+// An iteration admits what fits, then takes up to max_items blocks (the unit
+// of Sec. III: independent once the window's LLRs are present) from the
+// active frames (an equal share each, then the rest in admission order), so
+// a long frame spreads over several iterations while new frames join the next
+// one and can finish first.  Decoding a block needs only
+// its LLR window, so between iterations a frame's device state is its arena
+// range (LLRs, decoded bytes); path metrics live on chip for one block.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <deque>
+#include <vector>
+
+namespace vit {
+namespace serve {
+
+// Ring allocator over [0, cap): allocations are taken in order; memory is
+// reclaimed when the oldest live allocation is freed (frees may come in any
+// order).  All sizes are multiples of `align`.
+class Ring {
+ public:
+  explicit Ring(int64_t cap = 0, int64_t align = 256) : cap_(cap / align * align), align_(align) {}
+
+  int64_t capacity() const { return cap_; }
+  // bytes between the oldest live allocation and the next free offset
+  // (includes a skipped end segment while the ring is wrapped)
+  int64_t in_use() const {
+    if (live_.empty()) return 0;
+    const int64_t tail = live_.front().off;
+    return head_ > tail ? head_ - tail : cap_ - tail + head_;
+  }
+  int64_t round(int64_t b) const { return (b + align_ - 1) / align_ * align_; }
+
+  // Returns the offset, or -1 if `bytes` does not fit now.  *id receives a
+  // handle for free().
+  int64_t alloc(int64_t bytes, int64_t *id) {
+    bytes = round(bytes > 0 ? bytes : 1);
+    if (bytes > cap_) return -1;
+    int64_t off;
+    if (live_.empty()) {
+      head_ = 0;
+      off = 0;
+    } else {
+      const int64_t tail = live_.front().off;
+      if (head_ > tail) {                     // free space: [head, cap) and [0, tail)
+        if (head_ + bytes <= cap_) off = head_;
+        else if (bytes <= tail) off = 0;      // wrap; [head, cap) stays unused until reclaimed
+        else return -1;
+      } else {                                // wrapped: free space is [head, tail)
+        if (head_ + bytes <= tail) off = head_;
+        else return -1;
+      }
+    }
+    live_.push_back({off, bytes, false, next_id_});
+    *id = next_id_++;
+    head_ = off + bytes;
+    return off;
+  }
+
+  void free(int64_t id) {
+    // ids are increasing in allocation order: find by binary search
+    auto it = std::lower_bound(live_.begin(), live_.end(), id,
+                               [](const Entry &e, int64_t v) { return e.id < v; });
+    if (it == live_.end() || it->id != id || it->freed) return;
+    it->freed = true;
+    while (!live_.empty() && live_.front().freed) live_.pop_front();
+    if (live_.empty()) head_ = 0;
+  }
+
+  int64_t live_count() const { return (int64_t)live_.size(); }
+
+ private:
+  struct Entry {
+    int64_t off, bytes;
+    bool freed;
+    int64_t id;
+  };
+  int64_t cap_, align_;
+  int64_t head_ = 0;
+  int64_t next_id_ = 1;
+  std::deque<Entry> live_;
+};
+
+struct CodeShape {
+  int k, beta;
+  int64_t L, v1, v2;
+};
+
+struct Frame {
+  uint64_t tag;
+  int code;
+  int terminated;
+  int64_t n, N;
+  int64_t llr_src;     // byte offset of the LLRs in the host region
+  int64_t out_dst;     // byte offset of the decoded bytes in the host region
+  int64_t llr_bytes;
+  int64_t arrival_ns;
+  // set on admission
+  int64_t arena_llr = -1, arena_out = -1, ring_id = 0;
+  int64_t next_cs = 0;  // first core bit not yet launched
+};
+
+struct Item {          // one block, in arena byte offsets
+  int code;
+  int64_t llr_off, out_off;
+  int32_t s, e, cs, ce, flags, cost;
+};
+
+struct Copy {          // a byte range to move (ingest: host -> arena; egress: arena -> host)
+  int64_t src, dst, bytes;
+};
+
+struct Iteration {
+  std::vector<Item> items;
+  std::vector<Copy> ingest, egress;
+  std::vector<Frame> finishing;  // frames whose last block is in this iteration
+  int64_t admitted = 0;
+};
+
+class Core {
+ public:
+  Core(std::vector<CodeShape> shapes, int elem_bytes, int64_t arena_bytes, int max_frames, int max_items)
+      : shapes_(std::move(shapes)), elem_(elem_bytes), ring_(arena_bytes), max_frames_(max_frames),
+        max_items_(max_items) {}
+
+  // Arena bytes a frame needs (LLRs and decoded bytes, each 256-aligned).
+  int64_t arena_need(const Frame &f) const { return ring_.round(f.llr_bytes) + ring_.round((f.n + 7) / 8); }
+  bool fits_ever(const Frame &f) const { return arena_need(f) <= ring_.capacity(); }
+
+  void submit(const Frame &f) { pending_.push_back(f); }
+  size_t pending() const { return pending_.size(); }
+  size_t active() const { return active_.size(); }
+  int64_t frames_on_device() const { return on_device_; }
+  int64_t arena_in_use() const { return ring_.in_use(); }
+  bool has_work() const { return !pending_.empty() || !active_.empty(); }
+
+  // Admit what fits, then schedule up to max_items blocks.  Returns false if
+  // there is nothing to launch (no blocks, no copies).
+  bool next_iteration(Iteration *it) {
+    it->items.clear();
+    it->ingest.clear();
+    it->egress.clear();
+    it->finishing.clear();
+    it->admitted = 0;
+    while (!pending_.empty() && on_device_ < max_frames_) {
+      Frame f = pending_.front();
+      int64_t id;
+      const int64_t off = ring_.alloc(arena_need(f), &id);
+      if (off < 0) break;
+      pending_.pop_front();
+      f.arena_llr = off;
+      f.arena_out = off + ring_.round(f.llr_bytes);
+      f.ring_id = id;
+      f.next_cs = 0;
+      it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
+      active_.push_back(f);
+      ++on_device_;
+      ++it->admitted;
+    }
+    // Two passes over the active frames in admission order: first each frame
+    // gets an equal share of the iteration (at least one block), so short
+    // frames that joined late finish without waiting behind long ones; then
+    // what is left goes to the oldest frames.
+    int64_t room = max_items_;
+    const int64_t share = active_.empty() ? 0 : std::max<int64_t>(1, room / (int64_t)active_.size());
+    for (int pass = 0; pass < 2 && room > 0; ++pass) {
+      for (Frame &f : active_) {
+        if (room == 0) break;
+        take_blocks(f, pass == 0 ? std::min(share, room) : room, it, &room);
+      }
+    }
+    for (size_t i = 0; i < active_.size();) {
+      Frame &f = active_[i];
+      if (f.next_cs >= f.n) {
+        it->egress.push_back({f.arena_out, f.out_dst, (f.n + 7) / 8});
+        it->finishing.push_back(f);
+        active_.erase(active_.begin() + (std::ptrdiff_t)i);
+      } else {
+        ++i;
+      }
+    }
+    sort_items(it);
+    return !it->items.empty() || !it->ingest.empty() || !it->egress.empty();
+  }
+
+  // Drop every queued and admitted frame (after a device error), reporting
+  // each to `fn`; frames of launched iterations are not touched.
+  template <class Fn>
+  void fail_all(Fn fn) {
+    for (const Frame &f : pending_) fn(f);
+    pending_.clear();
+    for (const Frame &f : active_) {
+      fn(f);
+      ring_.free(f.ring_id);
+      --on_device_;
+    }
+    active_.clear();
+  }
+
+  // The iteration has finished on the device: release its frames' arena.
+  void retire(const Iteration &it) {
+    for (const Frame &f : it.finishing) {
+      ring_.free(f.ring_id);
+      --on_device_;
+    }
+  }
+
+ private:
+  // Group the items by code, each code's run longest first (the persistent
+  // kernel takes items in order), stable: a counting sort on (code, cost),
+  // linear in the item count since costs are at most L + v.
+  void sort_items(Iteration *it) {
+    const size_t n = it->items.size();
+    if (n < 2) return;
+    int32_t maxc = 0;
+    for (const Item &b : it->items) maxc = std::max(maxc, b.cost);
+    const size_t ncodes = shapes_.size(), span = (size_t)maxc + 1;
+    hist_.assign(ncodes * span + 1, 0);
+    // key: code-major, cost descending within a code
+    auto key = [&](const Item &b) { return (size_t)b.code * span + (size_t)(maxc - b.cost); };
+    for (const Item &b : it->items) ++hist_[key(b) + 1];
+    for (size_t i = 1; i < hist_.size(); ++i) hist_[i] += hist_[i - 1];
+    sorted_.resize(n);
+    for (const Item &b : it->items) sorted_[(size_t)hist_[key(b)]++] = b;
+    it->items.swap(sorted_);
+  }
+
+  // Append up to `limit` of f's next blocks (Sec. III geometry) to the iteration.
+  void take_blocks(Frame &f, int64_t limit, Iteration *it, int64_t *room) {
+    const CodeShape &sh = shapes_[f.code];
+    for (int64_t taken = 0; taken < limit && f.next_cs < f.n; ++taken) {
+      const int64_t cs = f.next_cs;
+      const int64_t ce = std::min(cs + sh.L, f.n);
+      const int64_t s = std::max<int64_t>(0, cs - sh.v1);
+      const int64_t e = std::min(f.N, ce + sh.v2);
+      Item b;
+      b.code = f.code;
+      b.llr_off = f.arena_llr;
+      b.out_off = f.arena_out;
+      b.s = (int32_t)s;
+      b.e = (int32_t)e;
+      b.cs = (int32_t)cs;
+      b.ce = (int32_t)ce;
+      b.flags = (s == 0 ? 1 : 0) | ((f.terminated && e == f.N) ? 2 : 0);
+      b.cost = (int32_t)(e - s);
+      it->items.push_back(b);
+      f.next_cs = ce;
+      --*room;
+    }
+  }
+
+  std::vector<CodeShape> shapes_;
+  std::vector<int64_t> hist_;
+  std::vector<Item> sorted_;
+  int elem_;
+  Ring ring_;
+  int max_frames_, max_items_;
+  std::deque<Frame> pending_;
+  std::deque<Frame> active_;
+  int64_t on_device_ = 0;
+};
+
+}  // namespace serve
+}  // namespace vit

@@ -1,0 +1,194 @@
+"""The serving loop on the GPU: frames submitted in waves while earlier ones
+are on the device come back identical to the same frames decoded alone on
+the GPU and by the CPU oracle; late short frames overtake a long one; queue
+limits and request validation."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import vref
+
+pytestmark = pytest.mark.gpu
+
+CODES = [(7, (0o171, 0o133)), (7, (0o133, 0o171, 0o165)), (9, (0o561, 0o753))]
+TUNE = [(64, 35, -1, 1), (128, 35, 10, 2), (64, 45, -1, 1)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_09337_amd as vit
+    return torch, vit
+
+
+def make_frames(rng, count, nmin, nmax, int8, code=None):
+    """(code_id, terminated, n, llr ndarray) for random (or the given) codes
+    and random lengths."""
+    out = []
+    for _ in range(count):
+        cid = int(rng.integers(0, len(CODES))) if code is None else code
+        k, gens = CODES[cid]
+        n = int(rng.integers(nmin, nmax + 1))
+        term = int(rng.random() < 0.8)
+        e = float(rng.uniform(1.0, 5.0))
+        llr = synth.awgn_llr(synth.encode(k, gens, synth.info_bits(n, rng), bool(term)), e, len(gens), rng)
+        if int8:
+            llr = vref.quantize_i8(llr, 8.0 * synth.noise_sigma(e, len(gens)) ** 2 / 2.0)
+        out.append((cid, term, n, llr))
+    return out
+
+
+def place(torch, frames, rng):
+    """Lay the frames' LLRs and output areas into one pinned host region (some
+    LLR offsets deliberately not 16-byte aligned).  Returns (host tensor,
+    [(llr_off, out_off)])."""
+    offs, pos = [], 0
+    for (_, _, n, llr) in frames:
+        pos += int(rng.integers(0, 3)) * 5
+        lo = pos
+        pos += llr.nbytes
+        oo = pos + 1
+        pos = oo + (n + 7) // 8
+        offs.append((lo, oo))
+    host = torch.zeros(pos + 64, dtype=torch.uint8).pin_memory()
+    h = host.numpy()
+    for (_, _, _, llr), (lo, _) in zip(frames, offs):
+        h[lo:lo + llr.nbytes] = llr.view(np.uint8)
+    return host, offs
+
+
+def requests(vit, host, frames, offs, tags):
+    r = np.zeros(len(tags), dtype=vit.REQUEST_DTYPE)
+    base = host.data_ptr()
+    for j, t in enumerate(tags):
+        cid, term, n, _ = frames[t]
+        lo, oo = offs[t]
+        r[j] = (cid, term, n, base + lo, base + oo, t, 0)
+    return r
+
+
+def expected_alone(torch, vit, frame, tune):
+    cid, term, n, llr = frame
+    k, gens = CODES[cid]
+    L, v, v1, _ = tune[cid]
+    out = vit.decode(vit.make_code(k, gens), torch.from_numpy(llr).cuda(), n, L, v, v1=None if v1 < 0 else v1,
+                     terminated=bool(term))
+    return out.cpu().numpy()
+
+
+def expected_oracle(frame, tune):
+    cid, term, n, llr = frame
+    k, gens = CODES[cid]
+    L, v, v1, _ = tune[cid]
+    v1 = v // 2 if v1 < 0 else v1
+    return synth.pack_bits(vref.decode_blocked(vref.make_code(k, list(gens)), llr, n, L, v1, v - v1, bool(term)))
+
+
+@pytest.mark.parametrize("int8", [True, False])
+def test_mix_equals_alone_and_oracle(dev, int8):
+    torch, vit = dev
+    rng = np.random.default_rng(11 if int8 else 12)
+    frames = make_frames(rng, 120, 20, 2500, int8)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    # a small arena and few slots and items, so that admission waits for
+    # memory and long frames span several iterations
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8 if int8 else vit.VIT_LLR_F32,
+                     arena_bytes=96 << 10, max_frames=10, max_items=48)
+    try:
+        order = rng.permutation(len(frames))
+        for wave in np.array_split(order, 8):
+            st, acc = srv.submit(requests(vit, host, frames, offs, [int(t) for t in wave]))
+            assert st == vit.VIT_OK and acc == len(wave)
+            time.sleep(0.002)
+        srv.drain(timeout_ms=60000)
+        comps = srv.poll()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames)))
+    assert (comps["status"] == 0).all()
+    assert (comps["done_ns"] >= comps["arrival_ns"]).all()
+    assert stats["completed"] == len(frames) and stats["failed"] == 0
+    assert stats["bits_completed"] == sum(f[2] for f in frames)
+    assert stats["iterations"] > 1
+    assert 1 <= stats["peak_frames_on_device"] <= 10
+    assert stats["peak_arena_bytes"] <= 96 << 10
+    assert 0 < stats["p50_ns"] <= stats["p99_ns"] <= stats["max_ns"]
+    h = host.numpy()
+    for t, fr in enumerate(frames):
+        lo, oo = offs[t]
+        got = h[oo:oo + (fr[2] + 7) // 8]
+        alone = expected_alone(torch, vit, fr, TUNE)
+        np.testing.assert_array_equal(got, alone, err_msg=f"frame {t} differs from its decode alone")
+        if t % 3 == 0:  # the oracle on a third of the frames keeps the test short
+            np.testing.assert_array_equal(got, expected_oracle(fr, TUNE), err_msg=f"frame {t} vs oracle")
+
+
+def test_late_short_frames_overtake_a_long_one(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(5)
+    long = make_frames(rng, 1, 16000, 16000, True, code=2)  # 250 blocks of 64 bits
+    short = make_frames(rng, 12, 40, 200, True)
+    frames = long + short
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64,
+                     max_items=16)
+    try:
+        assert srv.submit(requests(vit, host, frames, offs, [0])) == (vit.VIT_OK, 1)
+        assert srv.submit(requests(vit, host, frames, offs, list(range(1, len(frames))))) == (vit.VIT_OK,
+                                                                                             len(frames) - 1)
+        srv.drain(timeout_ms=60000)
+        comps = srv.poll()
+    finally:
+        srv.close()
+    done = {int(c["tag"]): int(c["done_ns"]) for c in comps}
+    assert len(done) == len(frames)
+    # the long frame needs 16 iterations; each short one (at most 4 blocks)
+    # gets a block in every iteration from the third at the latest
+    assert max(done[t] for t in range(1, len(frames))) < done[0]
+    h = host.numpy()
+    for t, fr in enumerate(frames):
+        lo, oo = offs[t]
+        np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
+
+
+def test_queue_limit_and_bad_requests(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(6)
+    frames = make_frames(rng, 20, 40, 300, True)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64,
+                     max_items=1024, max_pending=5)
+    try:
+        st, acc = srv.submit(requests(vit, host, frames, offs, list(range(20))))
+        assert st == vit.VIT_EBUSY and acc == 5
+        srv.drain(timeout_ms=30000)
+        bad = requests(vit, host, frames, offs, [5])
+        bad["llr"] = host.data_ptr() + host.numel() - 3  # runs past the host region
+        with pytest.raises(vit.VitError) as ei:
+            srv.submit(bad)
+        assert ei.value.status == vit.VIT_EINVAL
+        bad = requests(vit, host, frames, offs, [5])
+        bad["code_id"] = 3
+        with pytest.raises(vit.VitError):
+            srv.submit(bad)
+        st, acc = srv.submit(requests(vit, host, frames, offs, list(range(5, 10))))
+        assert st == vit.VIT_OK and acc == 5
+        srv.drain(timeout_ms=30000)
+        comps = srv.poll()
+        assert sorted(comps["tag"].tolist()) == list(range(10))
+        s = srv.stats(reset=True)
+        assert s["completed"] == 10 and srv.stats()["completed"] == 0
+    finally:
+        srv.close()
+    h = host.numpy()
+    for t in range(10):
+        lo, oo = offs[t]
+        np.testing.assert_array_equal(h[oo:oo + (frames[t][2] + 7) // 8], expected_alone(torch, vit, frames[t], TUNE))
