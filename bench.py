@@ -165,17 +165,18 @@ def bench_batched(vit, torch, args):
         vit.vit_quantize_i8(llr_d.data_ptr() + 4 * lo, cnt, sc, q_d.data_ptr() + lo, None)
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
+    frames_np = vit.frames_array(frames)  # the frame list as the C ABI reads it
     b = vit.Batch()
-    tunes = b.autotune(codes, frames, q_d, out)
+    tunes = b.autotune(codes, frames_np, q_d, out)
     stream = torch.cuda.current_stream()
     for _ in range(2):
-        b.decode(codes, frames, q_d, out, stream=stream)
+        b.decode(codes, frames_np, q_d, out, stream=stream)
     torch.cuda.synchronize()
     steps = max(3, args.steps // 2)
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record(stream)
     for _ in range(steps):
-        b.decode(codes, frames, q_d, out, stream=stream)
+        b.decode(codes, frames_np, q_d, out, stream=stream)
     s1.record(stream)
     torch.cuda.synchronize()
     ms = s0.elapsed_time(s1) / steps
@@ -185,7 +186,7 @@ def bench_batched(vit, torch, args):
                for f, bt in zip(frames, bits))
     # the same frames and shapes with the fp32 LLRs, for the int8 BER cost
     out32 = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
-    b.decode(codes, frames, llr_d, out32, tune=tunes)
+    b.decode(codes, frames_np, llr_d, out32, tune=tunes)
     torch.cuda.synchronize()
     g32 = out32.cpu().numpy()
     err32 = sum(int(np.sum(synth.unpack_bits(g32[f[4]:f[4] + (f[2] + 7) // 8], f[2]) != bt))

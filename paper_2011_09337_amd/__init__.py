@@ -6,7 +6,7 @@ include/vit.h.  This package only marshals torch device tensors into that ABI;
 PyTorch provides device memory and streams.
 """
 from . import _lib
-from ._lib import (codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
+from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy)
 from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_workspace_size)
@@ -14,7 +14,7 @@ from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LL
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
 
-__all__ = ["decode", "quantize", "Batch", "Server", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
+__all__ = ["decode", "quantize", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
@@ -73,9 +73,10 @@ def quantize(llr, scale, *, out=None, stream=None):
 class Batch:
     """A plan plus a device workspace for batched decoding (vit_decode_batch).
 
-    codes: list of vit_code; frames: list of (code_id, terminated, n,
-    llr_off, out_off).  The workspace is a torch uint8 tensor sized by
-    vit_batch_workspace_size for the largest frame list seen."""
+    codes: list of vit_code; frames: a FRAME_DTYPE array (passed to the C ABI
+    without copying) or a list of (code_id, terminated, n, llr_off, out_off).
+    The workspace is a torch uint8 tensor sized by vit_batch_workspace_size
+    for the largest frame list seen."""
 
     def __init__(self, device="cuda"):
         self.plan = vit_plan_create()

@@ -188,13 +188,25 @@ def codes_array(codes):
     return arr
 
 
+import numpy as _np
+
+# numpy layout of vit_frame: a frame list passes to the C ABI without copying
+FRAME_DTYPE = _np.dtype([("code_id", "<i4"), ("terminated", "<i4"), ("n", "<i8"), ("llr_off", "<i8"),
+                         ("out_off", "<i8")])
+
+
 def frames_array(frames):
-    """frames: iterable of (code_id, terminated, n, llr_off, out_off)."""
-    frames = list(frames)
-    arr = (vit_frame * len(frames))()
-    for i, (cid, term, n, lo, oo) in enumerate(frames):
-        arr[i].code_id, arr[i].terminated, arr[i].n, arr[i].llr_off, arr[i].out_off = cid, term, n, lo, oo
-    return arr
+    """A contiguous FRAME_DTYPE array from an iterable of (code_id,
+    terminated, n, llr_off, out_off) or from such an array (returned as is)."""
+    if isinstance(frames, _np.ndarray) and frames.dtype == FRAME_DTYPE and frames.flags.c_contiguous:
+        return frames
+    if isinstance(frames, _np.ndarray):
+        return _np.ascontiguousarray(frames, dtype=FRAME_DTYPE)
+    return _np.array([tuple(f) for f in frames], dtype=FRAME_DTYPE)
+
+
+def _fp(arr):
+    return arr.ctypes.data_as(_PF)
 
 
 def tunings_array(tunings):
@@ -216,14 +228,14 @@ def vit_plan_destroy(plan):
 
 def vit_batch_workspace_size(codes_arr, frames_arr, tune_arr=None):
     b = C.c_size_t()
-    _check(lib.vit_batch_workspace_size(codes_arr, len(codes_arr), frames_arr, len(frames_arr), tune_arr,
+    _check(lib.vit_batch_workspace_size(codes_arr, len(codes_arr), _fp(frames_arr), len(frames_arr), tune_arr,
                                         C.byref(b)))
     return b.value
 
 
 def vit_decode_batch(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, tune_arr,
                      ws_ptr, ws_bytes, stream=None):
-    return _check(lib.vit_decode_batch(plan, codes_arr, len(codes_arr), frames_arr, len(frames_arr), llr_ptr,
+    return _check(lib.vit_decode_batch(plan, codes_arr, len(codes_arr), _fp(frames_arr), len(frames_arr), llr_ptr,
                                        llr_count, llr_type, out_ptr, out_bytes, tune_arr, ws_ptr, ws_bytes,
                                        stream))
 
@@ -231,7 +243,7 @@ def vit_decode_batch(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, 
 def vit_plan_autotune(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, ws_ptr,
                       ws_bytes, stream=None):
     chosen = (vit_tuning * len(codes_arr))()
-    _check(lib.vit_plan_autotune(plan, codes_arr, len(codes_arr), frames_arr, len(frames_arr), llr_ptr, llr_count,
+    _check(lib.vit_plan_autotune(plan, codes_arr, len(codes_arr), _fp(frames_arr), len(frames_arr), llr_ptr, llr_count,
                                  llr_type, out_ptr, out_bytes, ws_ptr, ws_bytes, stream, chosen))
     return [(t.L, t.v, t.v1, t.waves_per_block) for t in chosen]
 

@@ -45,6 +45,12 @@ struct vit_plan {
   } key;
 
   std::map<std::string, vit_tuning> tuned;
+
+  // host scratch reused across calls (large per-call vectors would be mmap'd
+  // and page-faulted afresh every call)
+  std::vector<vit::WorkItem> sort_tmp;
+  std::vector<int64_t> sort_hist;
+  std::vector<std::pair<int64_t, int64_t>> out_ranges;
 };
 
 namespace {
@@ -111,7 +117,8 @@ int check_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, i
 // the items themselves, each code's run sorted by cost, longest first.
 int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
                     const vit_tuning *shape, int elem_bytes, WorkItem *items, int32_t *header,
-                    int64_t *max_stages) {
+                    int64_t *max_stages, std::vector<WorkItem> *tmp_buf = nullptr,
+                    std::vector<int64_t> *hist_buf = nullptr) {
   int64_t counts[kMaxCodes] = {0};
   for (int32_t f = 0; f < nframes; ++f) {
     const int c = frames[f].code_id;
@@ -151,9 +158,25 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
       if (max_stages && e - s > max_stages[c]) max_stages[c] = e - s;
     }
   }
+  // each code's run longest first: a stable counting sort on the cost
+  // (at most L + v stages), linear in the item count
+  std::vector<int64_t> own_hist;
+  std::vector<WorkItem> own_tmp;
+  std::vector<int64_t> &hist = hist_buf ? *hist_buf : own_hist;
+  std::vector<WorkItem> &tmp = tmp_buf ? *tmp_buf : own_tmp;
   for (int c = 0; c < ncodes; ++c) {
-    std::stable_sort(items + offs[c], items + offs[c] + counts[c],
-                     [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
+    WorkItem *run = items + offs[c];
+    const int64_t cnt = counts[c];
+    if (cnt > 1) {
+      int32_t maxc = 0;
+      for (int64_t i = 0; i < cnt; ++i) maxc = std::max(maxc, run[i].cost);
+      hist.assign((size_t)maxc + 2, 0);
+      for (int64_t i = 0; i < cnt; ++i) ++hist[(size_t)(maxc - run[i].cost) + 1];
+      for (size_t i = 1; i < hist.size(); ++i) hist[i] += hist[i - 1];
+      tmp.resize((size_t)cnt);
+      for (int64_t i = 0; i < cnt; ++i) tmp[(size_t)hist[(size_t)(maxc - run[i].cost)]++] = run[i];
+      std::copy(tmp.begin(), tmp.end(), run);
+    }
     header[kMaxCodes + c] = (int32_t)counts[c];
     header[2 * kMaxCodes + c] = (int32_t)offs[c];
   }
@@ -161,9 +184,9 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
 }
 
 int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes, int64_t llr_count,
-                 int llr_type, int64_t out_bytes) {
+                 int llr_type, int64_t out_bytes, std::vector<std::pair<int64_t, int64_t>> &outs) {
   const int elem = llr_type == VIT_LLR_I8 ? 1 : 4;
-  std::vector<std::pair<int64_t, int64_t>> outs;
+  outs.clear();
   outs.reserve(nframes);
   for (int32_t f = 0; f < nframes; ++f) {
     const vit_frame &fr = frames[f];
@@ -182,7 +205,8 @@ int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames,
     if (fr.out_off + nb > out_bytes) return api_fail(VIT_EINVAL, "frame %d: output beyond the buffer", f);
     outs.emplace_back(fr.out_off, fr.out_off + nb);
   }
-  std::sort(outs.begin(), outs.end());
+  // frames usually come with increasing outputs: sort only when they do not
+  if (!std::is_sorted(outs.begin(), outs.end())) std::sort(outs.begin(), outs.end());
   for (size_t i = 1; i < outs.size(); ++i)
     if (outs[i].first < outs[i - 1].second) return api_fail(VIT_EINVAL, "frames' output ranges overlap");
   return VIT_OK;
@@ -296,7 +320,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
   if (!llr || !out || !workspace) return api_fail(VIT_EINVAL, "NULL buffer");
   if (((uintptr_t)workspace & 255u) != 0) return api_fail(VIT_EINVAL, "workspace must be 256-byte aligned");
   if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8) return api_fail(VIT_EINVAL, "unknown llr_type %d", llr_type);
-  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
+  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges);
   if (st) return st;
   vit_tuning shape[kMaxCodes];
   st = resolve_shapes(plan, codes, ncodes, frames, nframes, llr_type, tune, shape);
@@ -323,25 +347,16 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
   int32_t *header = (int32_t *)stg;
   memset(header, 0, kHeaderBytes);
   int64_t max_stages[kMaxCodes];
-  build_items(codes, ncodes, frames, nframes, shape, elem, (WorkItem *)(stg + kHeaderBytes), header, max_stages);
+  build_items(codes, ncodes, frames, nframes, shape, elem, (WorkItem *)(stg + kHeaderBytes), header, max_stages,
+              &plan->sort_tmp, &plan->sort_hist);
 
   int dev = 0;
   he = hipGetDevice(&dev);
   if (he != hipSuccess) return vit::api_fail_hip(he, "hipGetDevice");
 
-  // launch shapes (LDS sized for the longest block a shape can produce)
-  vit::BatchLaunch bl[kMaxCodes];
-  for (int c = 0; c < ncodes; ++c) {
-    const int64_t vv = shape[c].v;
-    int unsupported = 0;
-    const char *why = "";
-    he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type == VIT_LLR_I8,
-                                (int64_t)shape[c].L + vv, shape[c].waves_per_block, &bl[c], &unsupported, &why);
-    if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
-    if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
-    if (llr_type == VIT_LLR_I8 && ((int64_t)shape[c].L + vv) * 128 * codes[c].beta >= ((int64_t)1 << 24))
+  for (int c = 0; c < ncodes; ++c)
+    if (llr_type == VIT_LLR_I8 && ((int64_t)shape[c].L + shape[c].v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
       return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
-  }
 
   // graph: reuse while buffers, codes and shapes are unchanged
   vit_plan::Key key;
@@ -359,6 +374,17 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     if (same) same = same_code(plan->key.codes[c], codes[c]) && same_tuning(plan->key.tune[c], shape[c]);
   }
   if (!same) {
+    // launch shapes (LDS sized for the longest block a shape can produce)
+    vit::BatchLaunch bl[kMaxCodes];
+    for (int c = 0; c < ncodes; ++c) {
+      int unsupported = 0;
+      const char *why = "";
+      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type == VIT_LLR_I8,
+                                  (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &bl[c], &unsupported,
+                                  &why);
+      if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
+      if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
+    }
     drop_graph(plan);
     he = hipGraphCreate(&plan->graph, 0);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphCreate");
@@ -416,7 +442,7 @@ int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, con
   if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
   int st = check_args(codes, ncodes, frames, nframes);
   if (st) return st;
-  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
+  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges);
   if (st) return st;
   hipEvent_t e0, e1;
   hipError_t he = hipEventCreate(&e0);

@@ -622,9 +622,13 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
   }
 }
 
-// Batched decode: persistent waves pull work items (one block of one frame
-// each, sorted by cost on the host) through an atomic counter until the list
-// is exhausted.  The counter and item count live in the caller's workspace.
+// Batched decode: persistent waves walk the work list (one block of one frame
+// per item, sorted by cost on the host, longest first) with a static stride:
+// wave w takes items w, w + W, w + 2W, ... for W waves in the grid.  Each
+// wave gets one item of every round of W, so with costs sorted the waves'
+// totals differ by at most one block; no atomics are needed (a single
+// device-wide counter serialises).  The item count and the offset of the
+// code's run live in the workspace header.
 template <int K, int BETA, bool STD, bool I8>
 __global__ __launch_bounds__(256) void vit_batch_kernel(BatchArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, I8>;
@@ -632,15 +636,12 @@ __global__ __launch_bounds__(256) void vit_batch_kernel(BatchArgs a, int lds_wor
   Dec D;
   D.setup(a.gen);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int wpb = (int)(blockDim.x >> 6);
   D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
-  const int nitems = a.header[kMaxCodes + a.code_index];
+  const int nitems = __builtin_amdgcn_readfirstlane(a.header[kMaxCodes + a.code_index]);
   const WorkItem *items = a.items + a.header[2 * kMaxCodes + a.code_index];
-  int32_t *counter = a.header + a.code_index;
-  for (;;) {
-    int idx = 0;
-    if (D.lane == 0) idx = atomicAdd(counter, 1);
-    idx = __builtin_amdgcn_readfirstlane(idx);
-    if (idx >= nitems) break;
+  const int nwaves = (int)gridDim.x * wpb;
+  for (int idx = (int)blockIdx.x * wpb + wid; idx < nitems; idx += nwaves) {
     const WorkItem it = items[idx];
     const char *base = (const char *)a.llr + it.llr_off;
     decode_block(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,

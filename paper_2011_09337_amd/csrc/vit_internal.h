@@ -37,8 +37,8 @@ struct WorkItem {
 };
 
 // Workspace header of a batched decode (device, int32 words): for code c,
-// [c] = next item to take (0 at launch), [kMaxCodes + c] = number of items,
-// [2*kMaxCodes + c] = offset of its first item in the item array.
+// [kMaxCodes + c] = number of items, [2*kMaxCodes + c] = offset of its first
+// item in the item array; words [0, kMaxCodes) are reserved (zero).
 constexpr int kMaxCodes = 8;
 constexpr size_t kHeaderBytes = 256;
 

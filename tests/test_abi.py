@@ -206,3 +206,13 @@ def test_batch_argument_errors(vit):
                                  FAKE, 10, None, 0x100000, 1 << 20, None)
     finally:
         vit.vit_plan_destroy(plan)
+
+
+def test_frame_layout(vit):
+    import ctypes
+    assert vit.FRAME_DTYPE.itemsize == ctypes.sizeof(vit._lib.vit_frame) == 32
+    for name, _ in vit._lib.vit_frame._fields_:
+        assert vit.FRAME_DTYPE.fields[name][1] == getattr(vit._lib.vit_frame, name).offset
+    a = vit.frames_array([(1, 0, 100, 7, 9)])
+    assert a.dtype == vit.FRAME_DTYPE and tuple(a[0]) == (1, 0, 100, 7, 9)
+    assert vit.frames_array(a) is a
