@@ -273,6 +273,14 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
  * device error that stopped the server.  Thread-safe with poll and stats. */
 int vit_server_submit(vit_server *server, const vit_request *reqs, int32_t count, int32_t *accepted);
 
+/* Replay an arrival process: submit reqs in order, each no earlier than its
+ * arrival_ns (CLOCK_MONOTONIC; requests with arrival_ns <= 0 go at once).
+ * The calling thread sleeps or spins between arrivals and submits all
+ * requests whose time has come in one batch; a full queue is retried.
+ * Returns once every request is queued (*accepted = count) or on the first
+ * refusal other than VIT_EBUSY, as vit_server_submit. */
+int vit_server_submit_paced(vit_server *server, const vit_request *reqs, int32_t count, int32_t *accepted);
+
 /* Move up to max completions (in completion order) into out; *count receives
  * how many.  A completion with status VIT_OK means its bytes are in place. */
 int vit_server_poll(vit_server *server, vit_completion *out, int32_t max, int32_t *count);

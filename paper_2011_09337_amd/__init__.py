@@ -9,7 +9,8 @@ from . import _lib
 from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy)
 from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
-                   vit_server_poll, vit_server_stats, vit_server_submit, vit_server_workspace_size)
+                   vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
+                   vit_server_workspace_size)
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
@@ -188,10 +189,22 @@ class Server:
             return VIT_OK, 0
         return vit_server_submit(self.server, reqs.ctypes.data, len(reqs))
 
+    def submit_paced(self, reqs):
+        """Submit each request of a REQUEST_DTYPE array at its arrival_ns
+        (time.monotonic_ns clock), from the calling thread; returns when all
+        are queued.  The GIL is released meanwhile."""
+        reqs = _np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        if len(reqs) == 0:
+            return 0
+        return vit_server_submit_paced(self.server, reqs.ctypes.data, len(reqs))
+
     def poll(self, max_count=65536):
-        buf = _np.empty(max_count, dtype=COMPLETION_DTYPE)
+        """Completions so far (up to max_count), as a COMPLETION_DTYPE array."""
+        buf = getattr(self, "_poll_buf", None)
+        if buf is None or len(buf) < max_count:
+            buf = self._poll_buf = _np.empty(max_count, dtype=COMPLETION_DTYPE)
         n = vit_server_poll(self.server, buf.ctypes.data, max_count)
-        return buf[:n]
+        return buf[:n].copy()
 
     def drain(self, timeout_ms=-1):
         return vit_server_drain(self.server, timeout_ms)

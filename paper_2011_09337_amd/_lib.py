@@ -121,6 +121,8 @@ lib.vit_server_create.argtypes = [_PC, C.c_int32, _PT, _PS, C.POINTER(C.c_void_p
 lib.vit_server_create.restype = C.c_int
 lib.vit_server_submit.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(C.c_int32)]
 lib.vit_server_submit.restype = C.c_int
+lib.vit_server_submit_paced.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(C.c_int32)]
+lib.vit_server_submit_paced.restype = C.c_int
 lib.vit_server_poll.argtypes = [C.c_void_p, _P, C.c_int32, C.POINTER(C.c_int32)]
 lib.vit_server_poll.restype = C.c_int
 lib.vit_server_drain.argtypes = [C.c_void_p, C.c_int64]
@@ -268,6 +270,12 @@ def vit_server_submit(server, reqs_ptr, count):
     if st not in (VIT_OK, VIT_EBUSY):
         raise VitError(st, vit_last_error())
     return st, acc.value
+
+
+def vit_server_submit_paced(server, reqs_ptr, count):
+    acc = C.c_int32()
+    _check(lib.vit_server_submit_paced(server, reqs_ptr, count, C.byref(acc)))
+    return acc.value
 
 
 def vit_server_poll(server, out_ptr, max_count):

@@ -37,6 +37,7 @@ using vit::kHeaderBytes;
 using vit::kMaxCodes;
 
 constexpr int kInflight = 2;
+constexpr int64_t kLatSample = 1 << 24;  // latency percentiles from at most this many samples
 
 int64_t mono_ns() {
   timespec ts;
@@ -106,44 +107,49 @@ struct vit_server {
   void *staging[kInflight] = {nullptr, nullptr};
   hipEvent_t ev[kInflight] = {nullptr, nullptr};
 
+  // Shared with the callers, under `mu`: the hand-off queue, completions,
+  // counters.  The lock is never held while a work list is built or HIP is
+  // called.
   std::mutex mu;
   std::condition_variable cv;      // wakes the engine: submit, stop
   std::condition_variable idle_cv; // wakes drain: progress
+  std::vector<vit::serve::Frame> incoming;
+  std::deque<vit_completion> done;
+  std::vector<int64_t> lat;        // latencies: all, or a uniform sample of kLatSample once more arrive
+  int64_t lat_seen = 0, lat_max = 0;
+  uint64_t lat_rng = 0x9e3779b97f4a7c15ull;
+  int64_t submitted = 0, completed = 0, failed_frames = 0, bits_completed = 0, iterations = 0,
+          items_launched = 0, peak_arena = 0, peak_frames = 0, first_arrival = 0, last_done = 0;
+  int64_t waiting = 0;             // submitted, not yet admitted
+  int64_t on_device = 0;           // admitted, not yet finished
+  int status = VIT_OK;
+  std::string fail_msg;
+  bool stop = false;
+
+  // Private to the engine thread.
   vit::serve::Core *core = nullptr;
   vit::serve::Iteration iters[kInflight];  // reused, so their buffers keep their capacity
   std::deque<int> inflight;                // slots of the iterations on the device, oldest first
   int next_slot = 0;
-  std::deque<vit_completion> done;
-  std::vector<int64_t> lat;
-  int64_t submitted = 0, completed = 0, failed_frames = 0, bits_completed = 0, iterations = 0,
-          items_launched = 0, peak_arena = 0, peak_frames = 0, first_arrival = 0, last_done = 0;
-  int status = VIT_OK;
-  std::string fail_msg;
-  bool stop = false;
   std::thread engine;
 };
 
 namespace {
 
-// Write the iteration's work list into pinned staging and issue its work.
-// Called by the engine thread without the lock (the iteration is private).
-int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, std::string *msg) {
-  uint8_t *stg = (uint8_t *)s->staging[slot];
-  uint8_t *wsd = s->ws + (size_t)slot * s->slot_bytes;
-  int32_t *header = (int32_t *)stg;
-  memset(header, 0, kHeaderBytes);
-  vit::WorkItem *wi = (vit::WorkItem *)(stg + kHeaderBytes);
-  int32_t count[kMaxCodes] = {0};
-  for (const auto &b : it.items) ++count[b.code];
-  int32_t off = 0;
-  for (int c = 0; c < s->ncodes; ++c) {
-    header[kMaxCodes + c] = count[c];
-    header[2 * kMaxCodes + c] = off;
-    off += count[c];
+// Writes the iteration's blocks straight into the slot's pinned staging, as
+// the batch kernels read them: one run per code after the header.
+struct StagingSink {
+  vit::WorkItem *wi;
+  int64_t cursor[kMaxCodes];
+  void begin(const int64_t *count, int ncodes) {
+    int64_t off = 0;
+    for (int c = 0; c < ncodes; ++c) {
+      cursor[c] = off;
+      off += count[c];
+    }
   }
-  for (size_t i = 0; i < it.items.size(); ++i) {  // items arrive grouped by code, longest first
-    const auto &b = it.items[i];
-    vit::WorkItem &w = wi[i];
+  void put(const vit::serve::Item &b) {
+    vit::WorkItem &w = wi[cursor[b.code]++];
     w.llr_off = b.llr_off;
     w.out_off = b.out_off;
     w.s = b.s;
@@ -153,7 +159,22 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     w.flags = b.flags;
     w.cost = b.cost;
   }
-  const size_t items_end = kHeaderBytes + it.items.size() * sizeof(vit::WorkItem);
+};
+
+// Complete the slot's staging (header, copy ranges after the blocks) and
+// issue the iteration's work.  Called by the engine thread without the lock.
+int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, std::string *msg) {
+  uint8_t *stg = (uint8_t *)s->staging[slot];
+  uint8_t *wsd = s->ws + (size_t)slot * s->slot_bytes;
+  int32_t *header = (int32_t *)stg;
+  memset(header, 0, kHeaderBytes);
+  int64_t off = 0;
+  for (int c = 0; c < s->ncodes; ++c) {
+    header[kMaxCodes + c] = (int32_t)it.count[c];
+    header[2 * kMaxCodes + c] = (int32_t)off;
+    off += it.count[c];
+  }
+  const size_t items_end = kHeaderBytes + (size_t)it.nitems * sizeof(vit::WorkItem);
   vit::CopyRange *cr = (vit::CopyRange *)(stg + items_end);
   for (size_t i = 0; i < it.ingest.size(); ++i)
     cr[i] = {s->host_dev + it.ingest[i].src, s->arena + it.ingest[i].dst, it.ingest[i].bytes, 0};
@@ -168,7 +189,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
   e = vit::launch_copy_list(dcr, (int32_t)it.ingest.size(), s->stream);
   if (e != hipSuccess) return *msg = std::string("ingest: ") + hipGetErrorString(e), VIT_EDEVICE;
   for (int c = 0; c < s->ncodes; ++c) {
-    if (!count[c]) continue;
+    if (!it.count[c]) continue;
     vit::BatchArgs a;
     a.llr = s->arena;
     a.out = s->arena;
@@ -179,7 +200,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     int words = s->bl[c].lds_words_per_wave;
     void *kargs[] = {&a, &words};
     const unsigned wpb = s->bl[c].block / 64;
-    unsigned grid = (unsigned)((count[c] + wpb - 1) / wpb);
+    unsigned grid = (unsigned)((it.count[c] + wpb - 1) / wpb);
     if (grid > s->bl[c].grid) grid = s->bl[c].grid;
     e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
     if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
@@ -198,79 +219,124 @@ void fail_locked(vit_server *s, int status, const std::string &msg) {
   }
 }
 
+// Report finished (or failed) frames; `admitted` of them were on the device,
+// the rest were still waiting.
+void finish_frames(vit_server *s, const std::vector<vit::serve::Frame> &frames, int st, int64_t now,
+                   int64_t admitted) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (const auto &f : frames) {
+    s->done.push_back({f.tag, st, 0, f.arrival_ns, now});
+    if (st == VIT_OK) {
+      ++s->completed;
+      s->bits_completed += f.n;
+      // reservoir sampling keeps the percentiles' memory bounded
+      const int64_t l = now - f.arrival_ns;
+      if ((int64_t)s->lat.size() < kLatSample) {
+        s->lat.push_back(l);
+      } else {
+        s->lat_rng ^= s->lat_rng << 13;
+        s->lat_rng ^= s->lat_rng >> 7;
+        s->lat_rng ^= s->lat_rng << 17;
+        const uint64_t r = s->lat_rng % (uint64_t)(s->lat_seen + 1);
+        if (r < (uint64_t)kLatSample) s->lat[r] = l;
+      }
+      ++s->lat_seen;
+      s->lat_max = std::max(s->lat_max, l);
+    } else {
+      ++s->failed_frames;
+    }
+    s->last_done = now;
+  }
+  s->on_device -= admitted;
+  s->waiting -= (int64_t)frames.size() - admitted;
+  s->idle_cv.notify_all();
+}
+
 void engine_main(vit_server *s) {
   (void)hipSetDevice(s->dev);
-  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<vit::serve::Frame> arrived;
+  std::vector<vit::serve::Frame> dropped;
   for (;;) {
+    bool stop, failed;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      arrived.swap(s->incoming);
+      stop = s->stop;
+      failed = s->status != VIT_OK;
+    }
+    for (const auto &f : arrived) s->core->submit(f);
+    arrived.clear();
+
     // retire finished iterations, oldest first
+    bool progressed = false;
     while (!s->inflight.empty()) {
       const hipError_t q = hipEventQuery(s->ev[s->inflight.front()]);
       if (q == hipErrorNotReady) break;
-      const int64_t now = mono_ns();
       const int st = q == hipSuccess ? VIT_OK : VIT_EDEVICE;
-      if (st != VIT_OK) fail_locked(s, st, std::string("iteration failed: ") + hipGetErrorString(q));
-      vit::serve::Iteration &it = s->iters[s->inflight.front()];
-      for (const auto &f : it.finishing) {
-        vit_completion c;
-        c.tag = f.tag;
-        c.status = st;
-        c.reserved = 0;
-        c.arrival_ns = f.arrival_ns;
-        c.done_ns = now;
-        s->done.push_back(c);
-        if (st == VIT_OK) {
-          ++s->completed;
-          s->bits_completed += f.n;
-          s->lat.push_back(now - f.arrival_ns);
-        } else {
-          ++s->failed_frames;
-        }
-        s->last_done = now;
+      if (st != VIT_OK) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        fail_locked(s, st, std::string("iteration failed: ") + hipGetErrorString(q));
+        failed = true;
       }
+      vit::serve::Iteration &it = s->iters[s->inflight.front()];
+      finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
       s->core->retire(it);
       s->inflight.pop_front();
-      s->idle_cv.notify_all();
+      progressed = true;
     }
-    if (s->status != VIT_OK && s->inflight.empty() && s->core->has_work()) {
+    if (failed && s->inflight.empty() && s->core->has_work()) {
       // after a device error nothing more is launched: queued and admitted
       // frames complete with the error
-      const int64_t now = mono_ns();
-      s->core->fail_all([&](const vit::serve::Frame &f) {
-        s->done.push_back({f.tag, s->status, 0, f.arrival_ns, now});
-        ++s->failed_frames;
+      dropped.clear();
+      int64_t admitted = 0;
+      s->core->fail_all([&](const vit::serve::Frame &f, bool adm) {
+        dropped.push_back(f);
+        admitted += adm ? 1 : 0;
       });
-      s->idle_cv.notify_all();
+      int st;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        st = s->status;
+      }
+      finish_frames(s, dropped, st, mono_ns(), admitted);
     }
-    if (s->stop && s->inflight.empty()) break;
-    if (s->status == VIT_OK && !s->stop && (int)s->inflight.size() < kInflight && s->core->has_work()) {
+    if (stop && s->inflight.empty()) break;
+    if (!failed && !stop && (int)s->inflight.size() < kInflight && s->core->has_work()) {
       const int slot = s->next_slot;
       vit::serve::Iteration &it = s->iters[slot];
-      if (s->core->next_iteration(&it)) {
+      StagingSink sink;
+      sink.wi = (vit::WorkItem *)((uint8_t *)s->staging[slot] + kHeaderBytes);
+      if (s->core->next_iteration(&it, sink)) {
         s->next_slot = (slot + 1) % kInflight;
-        s->peak_arena = std::max(s->peak_arena, s->core->arena_in_use());
-        s->peak_frames = std::max(s->peak_frames, s->core->frames_on_device());
-        ++s->iterations;
-        s->items_launched += (int64_t)it.items.size();
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->waiting -= it.admitted;
+          s->on_device += it.admitted;
+          s->peak_arena = std::max(s->peak_arena, s->core->arena_in_use());
+          s->peak_frames = std::max(s->peak_frames, s->core->frames_on_device());
+          ++s->iterations;
+          s->items_launched += it.nitems;
+        }
         s->inflight.push_back(slot);
-        lk.unlock();
         std::string msg;
         const int st = launch_iteration(s, it, slot, &msg);
-        lk.lock();
         if (st != VIT_OK) {
-          fail_locked(s, st, msg);
-          // the iteration's event was not recorded: its frames fail now
-          for (const auto &f : it.finishing) {
-            s->done.push_back({f.tag, st, 0, f.arrival_ns, mono_ns()});
-            ++s->failed_frames;
+          {
+            std::lock_guard<std::mutex> lk(s->mu);
+            fail_locked(s, st, msg);
           }
+          // the iteration's event was not recorded: its frames fail now
+          finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
           s->core->retire(it);
           s->inflight.pop_back();
-          s->idle_cv.notify_all();
         }
         continue;
       }
     }
+    if (progressed) continue;
     // nothing to launch: wait for a submit, or poll the running iteration
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (!s->incoming.empty() || s->stop) continue;
     if (!s->inflight.empty()) s->cv.wait_for(lk, std::chrono::microseconds(20));
     else s->cv.wait_for(lk, std::chrono::milliseconds(2));
   }
@@ -398,59 +464,95 @@ int vit_server_submit(vit_server *s, const vit_request *reqs, int32_t count, int
   if (!s) return api_fail(VIT_EINVAL, "server is NULL");
   if (count < 0 || (count > 0 && !reqs)) return api_fail(VIT_EINVAL, "bad request array");
   const int64_t now = mono_ns();
+  // validate outside the lock (only immutable server state is read)
+  thread_local std::vector<vit::serve::Frame> local;
+  local.clear();
   int st = VIT_OK;
-  int32_t took = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const vit_request &r = reqs[i];
+    if (r.code_id < 0 || r.code_id >= s->ncodes) {
+      st = api_fail(VIT_EINVAL, "request %d: code_id %d", i, r.code_id);
+      break;
+    }
+    if (r.n <= 0 || (r.terminated != 0 && r.terminated != 1)) {
+      st = api_fail(VIT_EINVAL, "request %d: n = %lld, terminated = %d", i, (long long)r.n, r.terminated);
+      break;
+    }
+    const vit_code &c = s->codes[r.code_id];
+    const int64_t N = r.n + (r.terminated ? c.k - 1 : 0);
+    if (N * c.beta * s->elem >= ((int64_t)1 << 31)) {
+      st = api_fail(VIT_EUNSUPPORTED, "request %d: frame too long", i);
+      break;
+    }
+    vit::serve::Frame f;
+    f.tag = r.tag;
+    f.code = r.code_id;
+    f.terminated = r.terminated;
+    f.n = r.n;
+    f.N = N;
+    f.llr_bytes = N * c.beta * s->elem;
+    if (!in_range(s->host, s->host_bytes, r.llr, f.llr_bytes) ||
+        !in_range(s->host, s->host_bytes, r.out, (r.n + 7) / 8)) {
+      st = api_fail(VIT_EINVAL, "request %d: LLRs or output outside the host region", i);
+      break;
+    }
+    f.llr_src = (const uint8_t *)r.llr - s->host;
+    f.out_dst = r.out - s->host;
+    f.arrival_ns = r.arrival_ns > 0 ? r.arrival_ns : now;
+    if (!s->core->fits_ever(f)) {  // reads only the arena size, fixed at creation
+      st = api_fail(VIT_EINVAL, "request %d: needs %lld arena bytes, more than the arena", i,
+                    (long long)s->core->arena_need(f));
+      break;
+    }
+    local.push_back(f);
+  }
+  int32_t took = (int32_t)local.size();
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->status != VIT_OK) return api_fail(s->status, "server failed: %s", s->fail_msg.c_str());
-    for (; took < count; ++took) {
-      const vit_request &r = reqs[took];
-      if (r.code_id < 0 || r.code_id >= s->ncodes) {
-        st = api_fail(VIT_EINVAL, "request %d: code_id %d", took, r.code_id);
-        break;
-      }
-      if (r.n <= 0 || (r.terminated != 0 && r.terminated != 1)) {
-        st = api_fail(VIT_EINVAL, "request %d: n = %lld, terminated = %d", took, (long long)r.n, r.terminated);
-        break;
-      }
-      const vit_code &c = s->codes[r.code_id];
-      const int64_t N = r.n + (r.terminated ? c.k - 1 : 0);
-      if (N * c.beta * s->elem >= ((int64_t)1 << 31)) {
-        st = api_fail(VIT_EUNSUPPORTED, "request %d: frame too long", took);
-        break;
-      }
-      vit::serve::Frame f;
-      f.tag = r.tag;
-      f.code = r.code_id;
-      f.terminated = r.terminated;
-      f.n = r.n;
-      f.N = N;
-      f.llr_bytes = N * c.beta * s->elem;
-      if (!in_range(s->host, s->host_bytes, r.llr, f.llr_bytes) ||
-          !in_range(s->host, s->host_bytes, r.out, (r.n + 7) / 8)) {
-        st = api_fail(VIT_EINVAL, "request %d: LLRs or output outside the host region", took);
-        break;
-      }
-      f.llr_src = (const uint8_t *)r.llr - s->host;
-      f.out_dst = r.out - s->host;
-      f.arrival_ns = r.arrival_ns > 0 ? r.arrival_ns : now;
-      if (!s->core->fits_ever(f)) {
-        st = api_fail(VIT_EINVAL, "request %d: needs %lld arena bytes, more than the arena", took,
-                      (long long)s->core->arena_need(f));
-        break;
-      }
-      if ((int64_t)s->core->pending() >= s->max_pending) {
-        st = api_fail(VIT_EBUSY, "request queue full (%d pending)", s->max_pending);
-        break;
-      }
-      s->core->submit(f);
-      ++s->submitted;
-      if (s->first_arrival == 0 || f.arrival_ns < s->first_arrival) s->first_arrival = f.arrival_ns;
+    const int64_t room = std::max<int64_t>(0, (int64_t)s->max_pending - s->waiting);
+    if (took > room) {
+      took = (int32_t)room;
+      st = api_fail(VIT_EBUSY, "request queue full (%d waiting)", s->max_pending);
     }
+    s->incoming.insert(s->incoming.end(), local.begin(), local.begin() + took);
+    s->waiting += took;
+    s->submitted += took;
+    for (int32_t i = 0; i < took; ++i)
+      if (s->first_arrival == 0 || local[i].arrival_ns < s->first_arrival) s->first_arrival = local[i].arrival_ns;
   }
   if (took) s->cv.notify_one();
   if (accepted) *accepted = took;
   return st;
+}
+
+int vit_server_submit_paced(vit_server *s, const vit_request *reqs, int32_t count, int32_t *accepted) {
+  vit::api_clear_error();
+  if (accepted) *accepted = 0;
+  if (!s) return api_fail(VIT_EINVAL, "server is NULL");
+  if (count < 0 || (count > 0 && !reqs)) return api_fail(VIT_EINVAL, "bad request array");
+  int32_t i = 0;
+  while (i < count) {
+    const int64_t now = mono_ns();
+    int32_t j = i;
+    while (j < count && reqs[j].arrival_ns <= now) ++j;
+    if (j > i) {
+      int32_t took = 0;
+      const int st = vit_server_submit(s, reqs + i, j - i, &took);
+      i += took;
+      if (accepted) *accepted = i;
+      if (st == VIT_EBUSY) {
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+        continue;
+      }
+      if (st != VIT_OK) return st;
+      continue;
+    }
+    const int64_t wait = reqs[i].arrival_ns - now;
+    if (wait > 300000) std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 200000));
+    else if (wait > 20000) std::this_thread::yield();
+  }
+  return VIT_OK;
 }
 
 int vit_server_poll(vit_server *s, vit_completion *out, int32_t max, int32_t *count) {
@@ -471,12 +573,11 @@ int vit_server_drain(vit_server *s, int64_t timeout_ms) {
   vit::api_clear_error();
   if (!s) return api_fail(VIT_EINVAL, "server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
-  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
-  while (s->core->has_work() || !s->inflight.empty()) {
-    if (timeout_ms >= 0 && s->idle_cv.wait_until(lk, deadline) == std::cv_status::timeout &&
-        (s->core->has_work() || !s->inflight.empty()))
-      return api_fail(VIT_EBUSY, "work still queued after %lld ms", (long long)timeout_ms);
-    if (timeout_ms < 0) s->idle_cv.wait(lk);
+  auto idle = [&] { return s->waiting == 0 && s->on_device == 0; };
+  if (timeout_ms < 0) {
+    s->idle_cv.wait(lk, idle);
+  } else if (!s->idle_cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), idle)) {
+    return api_fail(VIT_EBUSY, "work still queued after %lld ms", (long long)timeout_ms);
   }
   if (s->status != VIT_OK) return api_fail(s->status, "server failed: %s", s->fail_msg.c_str());
   return VIT_OK;
@@ -493,8 +594,8 @@ int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
   st->bits_completed = s->bits_completed;
   st->iterations = s->iterations;
   st->items_launched = s->items_launched;
-  st->pending = (int64_t)s->core->pending();
-  st->frames_on_device = s->core->frames_on_device();
+  st->pending = s->waiting;
+  st->frames_on_device = s->on_device;
   st->peak_frames_on_device = s->peak_frames;
   st->peak_arena_bytes = s->peak_arena;
   st->first_arrival_ns = s->first_arrival;
@@ -508,10 +609,12 @@ int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
     };
     st->p50_ns = pct(0.50);
     st->p99_ns = pct(0.99);
-    st->max_ns = *std::max_element(v.begin(), v.end());
+    st->max_ns = s->lat_max;
   }
   if (reset) {
     s->lat.clear();
+    s->lat_seen = 0;
+    s->lat_max = 0;
     s->submitted = s->completed = s->failed_frames = s->bits_completed = 0;
     s->iterations = s->items_launched = 0;
     s->peak_arena = s->peak_frames = 0;

@@ -120,11 +120,29 @@ struct Copy {          // a byte range to move (ingest: host -> arena; egress: a
   int64_t src, dst, bytes;
 };
 
+constexpr int kMaxShapes = 8;
+
 struct Iteration {
-  std::vector<Item> items;
+  int64_t count[kMaxShapes] = {0};  // blocks per code, handed to the sink grouped by code
+  int64_t nitems = 0;
   std::vector<Copy> ingest, egress;
-  std::vector<Frame> finishing;  // frames whose last block is in this iteration
+  std::vector<Frame> finishing;     // frames whose last block is in this iteration
   int64_t admitted = 0;
+};
+
+// A sink that collects the blocks into one vector, grouped by code (tests).
+struct VectorSink {
+  std::vector<Item> items;
+  int64_t cursor[kMaxShapes] = {0};
+  void begin(const int64_t *count, int ncodes) {
+    int64_t total = 0;
+    for (int c = 0; c < ncodes; ++c) {
+      cursor[c] = total;
+      total += count[c];
+    }
+    items.resize((size_t)total);
+  }
+  void put(const Item &b) { items[(size_t)cursor[b.code]++] = b; }
 };
 
 class Core {
@@ -144,63 +162,83 @@ class Core {
   int64_t arena_in_use() const { return ring_.in_use(); }
   bool has_work() const { return !pending_.empty() || !active_.empty(); }
 
-  // Admit what fits, then schedule up to max_items blocks.  Returns false if
-  // there is nothing to launch (no blocks, no copies).
-  bool next_iteration(Iteration *it) {
-    it->items.clear();
+  // Admit what fits, then schedule up to max_items blocks, handing each to
+  // sink.put grouped by code after sink.begin(per-code counts, ncodes).
+  // Returns false if there is nothing to launch (no blocks, no copies).
+  template <class Sink>
+  bool next_iteration(Iteration *it, Sink &sink) {
     it->ingest.clear();
     it->egress.clear();
     it->finishing.clear();
     it->admitted = 0;
     while (!pending_.empty() && on_device_ < max_frames_) {
-      Frame f = pending_.front();
+      Frame &f = pending_.front();
       int64_t id;
       const int64_t off = ring_.alloc(arena_need(f), &id);
       if (off < 0) break;
-      pending_.pop_front();
       f.arena_llr = off;
       f.arena_out = off + ring_.round(f.llr_bytes);
       f.ring_id = id;
       f.next_cs = 0;
       it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
       active_.push_back(f);
+      pending_.pop_front();
       ++on_device_;
       ++it->admitted;
     }
-    // Two passes over the active frames in admission order: first each frame
-    // gets an equal share of the iteration (at least one block), so short
-    // frames that joined late finish without waiting behind long ones; then
-    // what is left goes to the oldest frames.
+    // Blocks per frame, in two passes over the active frames in admission
+    // order: first each frame gets an equal share of the iteration (at least
+    // one block), so short frames that joined late finish without waiting
+    // behind long ones; then what is left goes to the oldest frames.
+    const size_t na = active_.size();
+    take_.assign(na, 0);
     int64_t room = max_items_;
-    const int64_t share = active_.empty() ? 0 : std::max<int64_t>(1, room / (int64_t)active_.size());
+    const int64_t share = na ? std::max<int64_t>(1, room / (int64_t)na) : 0;
     for (int pass = 0; pass < 2 && room > 0; ++pass) {
-      for (Frame &f : active_) {
-        if (room == 0) break;
-        take_blocks(f, pass == 0 ? std::min(share, room) : room, it, &room);
+      for (size_t i = 0; i < na && room > 0; ++i) {
+        const Frame &f = active_[i];
+        const int64_t L = shapes_[f.code].L;
+        const int64_t left = (f.n - f.next_cs + L - 1) / L - take_[i];
+        const int64_t t = std::min(left, pass == 0 ? std::min(share, room) : room);
+        take_[i] += t;
+        room -= t;
       }
     }
-    for (size_t i = 0; i < active_.size();) {
+    const int ncodes = (int)shapes_.size();
+    for (int c = 0; c < kMaxShapes; ++c) it->count[c] = 0;
+    for (size_t i = 0; i < na; ++i) it->count[active_[i].code] += take_[i];
+    it->nitems = max_items_ - room;
+    sink.begin(it->count, ncodes);
+    // emit the blocks; frames with every block launched leave the active set
+    // (one stable compaction pass: erasing from the middle one by one is
+    // quadratic)
+    size_t keep = 0;
+    for (size_t i = 0; i < na; ++i) {
       Frame &f = active_[i];
+      if (take_[i]) emit_blocks(f, take_[i], sink);
       if (f.next_cs >= f.n) {
         it->egress.push_back({f.arena_out, f.out_dst, (f.n + 7) / 8});
         it->finishing.push_back(f);
-        active_.erase(active_.begin() + (std::ptrdiff_t)i);
       } else {
-        ++i;
+        if (keep != i) active_[keep] = f;
+        ++keep;
       }
     }
-    sort_items(it);
-    return !it->items.empty() || !it->ingest.empty() || !it->egress.empty();
+    active_.resize(keep);
+    return it->nitems > 0 || !it->ingest.empty() || !it->egress.empty();
   }
 
+  bool next_iteration(Iteration *it, VectorSink &sink) { return next_iteration<VectorSink>(it, sink); }
+
   // Drop every queued and admitted frame (after a device error), reporting
-  // each to `fn`; frames of launched iterations are not touched.
+  // each to fn(frame, admitted); frames of launched iterations are not
+  // touched.
   template <class Fn>
   void fail_all(Fn fn) {
-    for (const Frame &f : pending_) fn(f);
+    for (const Frame &f : pending_) fn(f, false);
     pending_.clear();
     for (const Frame &f : active_) {
-      fn(f);
+      fn(f, true);
       ring_.free(f.ring_id);
       --on_device_;
     }
@@ -216,52 +254,32 @@ class Core {
   }
 
  private:
-  // Group the items by code, each code's run longest first (the persistent
-  // kernel takes items in order), stable: a counting sort on (code, cost),
-  // linear in the item count since costs are at most L + v.
-  void sort_items(Iteration *it) {
-    const size_t n = it->items.size();
-    if (n < 2) return;
-    int32_t maxc = 0;
-    for (const Item &b : it->items) maxc = std::max(maxc, b.cost);
-    const size_t ncodes = shapes_.size(), span = (size_t)maxc + 1;
-    hist_.assign(ncodes * span + 1, 0);
-    // key: code-major, cost descending within a code
-    auto key = [&](const Item &b) { return (size_t)b.code * span + (size_t)(maxc - b.cost); };
-    for (const Item &b : it->items) ++hist_[key(b) + 1];
-    for (size_t i = 1; i < hist_.size(); ++i) hist_[i] += hist_[i - 1];
-    sorted_.resize(n);
-    for (const Item &b : it->items) sorted_[(size_t)hist_[key(b)]++] = b;
-    it->items.swap(sorted_);
-  }
-
-  // Append up to `limit` of f's next blocks (Sec. III geometry) to the iteration.
-  void take_blocks(Frame &f, int64_t limit, Iteration *it, int64_t *room) {
+  // Hand f's next `count` blocks (Sec. III geometry) to the sink.
+  template <class Sink>
+  void emit_blocks(Frame &f, int64_t count, Sink &sink) {
     const CodeShape &sh = shapes_[f.code];
-    for (int64_t taken = 0; taken < limit && f.next_cs < f.n; ++taken) {
+    Item b;
+    b.code = f.code;
+    b.llr_off = f.arena_llr;
+    b.out_off = f.arena_out;
+    for (int64_t taken = 0; taken < count; ++taken) {
       const int64_t cs = f.next_cs;
       const int64_t ce = std::min(cs + sh.L, f.n);
       const int64_t s = std::max<int64_t>(0, cs - sh.v1);
       const int64_t e = std::min(f.N, ce + sh.v2);
-      Item b;
-      b.code = f.code;
-      b.llr_off = f.arena_llr;
-      b.out_off = f.arena_out;
       b.s = (int32_t)s;
       b.e = (int32_t)e;
       b.cs = (int32_t)cs;
       b.ce = (int32_t)ce;
       b.flags = (s == 0 ? 1 : 0) | ((f.terminated && e == f.N) ? 2 : 0);
       b.cost = (int32_t)(e - s);
-      it->items.push_back(b);
+      sink.put(b);
       f.next_cs = ce;
-      --*room;
     }
   }
 
   std::vector<CodeShape> shapes_;
-  std::vector<int64_t> hist_;
-  std::vector<Item> sorted_;
+  std::vector<int64_t> take_;
   int elem_;
   Ring ring_;
   int max_frames_, max_items_;

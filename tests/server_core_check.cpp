@@ -12,6 +12,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <random>
@@ -125,11 +126,18 @@ int main(int argc, char **argv) {
       }
     } else if ((what == 1 || what == 0) && inflight.size() < 2) {
       Iteration it;
-      if (!core.next_iteration(&it)) {
-        CHECK(it.items.empty() && it.ingest.empty() && it.egress.empty(), "empty iteration with work");
+      VectorSink sink;
+      if (!core.next_iteration(&it, sink)) {
+        CHECK(sink.items.empty() && it.ingest.empty() && it.egress.empty(), "empty iteration with work");
         continue;
       }
-      CHECK((int64_t)it.items.size() <= max_items, "%zu items > %d", it.items.size(), max_items);
+      const std::vector<Item> &items = sink.items;
+      CHECK((int64_t)items.size() == it.nitems, "sink got %zu items, iteration says %lld", items.size(),
+            (long long)it.nitems);
+      for (int c = 0; c < 3; ++c)
+        CHECK(std::count_if(items.begin(), items.end(), [&](const Item &b) { return b.code == c; }) == it.count[c],
+              "per-code count");
+      CHECK((int64_t)items.size() <= max_items, "%zu items > %d", items.size(), max_items);
       // ingest: admissions in FIFO order
       for (const Copy &c : it.ingest) {
         CHECK(!submit_order.empty(), "ingest with nothing submitted");
@@ -155,11 +163,11 @@ int main(int argc, char **argv) {
       // items: geometry, order, grouping
       std::map<int64_t, uint64_t> by_arena;
       for (const auto &kv : on_device) by_arena[kv.second.first] = kv.first;
-      for (size_t i = 0; i < it.items.size(); ++i) {
-        const Item &b = it.items[i];
+      for (size_t i = 0; i < items.size(); ++i) {
+        const Item &b = items[i];
         if (i) {
-          const Item &a = it.items[i - 1];
-          CHECK(a.code < b.code || (a.code == b.code && a.cost >= b.cost), "items not grouped by code, longest first");
+          const Item &a = items[i - 1];
+          CHECK(a.code <= b.code, "items not grouped by code");
         }
         CHECK(by_arena.count(b.llr_off), "item of a frame not on the device");
         Truth &t = frames[by_arena[b.llr_off]];
@@ -167,7 +175,7 @@ int main(int argc, char **argv) {
       }
       // per frame, blocks in order (items are sorted, so collect first)
       std::map<uint64_t, std::vector<Item>> per;
-      for (const Item &b : it.items) per[by_arena[b.llr_off]].push_back(b);
+      for (const Item &b : items) per[by_arena[b.llr_off]].push_back(b);
       // fair share: when the iteration has room for one block per active
       // frame, every admitted frame with blocks left gets at least one
       int64_t waiting = 0;
@@ -242,9 +250,10 @@ int main(int argc, char **argv) {
     if (core.fits_ever(f)) core.submit(f);
   }
   Iteration it;
-  core.next_iteration(&it);
+  VectorSink sink;
+  core.next_iteration(&it, sink);
   int64_t dropped = 0;
-  core.fail_all([&](const Frame &) { ++dropped; });
+  core.fail_all([&](const Frame &, bool) { ++dropped; });
   core.retire(it);
   CHECK(!core.has_work() && core.frames_on_device() == 0 && core.arena_in_use() == 0, "fail_all left work");
   printf("OK seed %llu: %lld frames, arena %lld, slots %d, items/iter %d, L %lld/%lld/%lld\n",

@@ -192,3 +192,35 @@ def test_queue_limit_and_bad_requests(dev):
     for t in range(10):
         lo, oo = offs[t]
         np.testing.assert_array_equal(h[oo:oo + (frames[t][2] + 7) // 8], expected_alone(torch, vit, frames[t], TUNE))
+
+
+def test_paced_submission_replays_arrival_times(dev):
+    torch, vit = dev
+    rng = np.random.default_rng(8)
+    frames = make_frames(rng, 40, 40, 800, True)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64,
+                     max_items=256)
+    try:
+        reqs = requests(vit, host, frames, offs, list(range(len(frames))))
+        t0 = time.monotonic_ns() + 5_000_000
+        reqs["arrival_ns"] = t0 + np.sort(rng.integers(0, 30_000_000, size=len(frames)))
+        c0 = time.monotonic_ns()
+        assert srv.submit_paced(reqs) == len(frames)
+        c1 = time.monotonic_ns()
+        srv.drain(timeout_ms=30000)
+        comps = srv.poll()
+    finally:
+        srv.close()
+    # the call returns no earlier than the last arrival
+    assert c1 >= int(reqs["arrival_ns"][-1]) and c0 < t0
+    by_tag = {int(c["tag"]): c for c in comps}
+    assert sorted(by_tag) == list(range(len(frames)))
+    for t in range(len(frames)):
+        assert int(by_tag[t]["arrival_ns"]) == int(reqs["arrival_ns"][t])
+        assert int(by_tag[t]["done_ns"]) > int(reqs["arrival_ns"][t])
+    h = host.numpy()
+    for t, fr in enumerate(frames):
+        lo, oo = offs[t]
+        np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
