@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--L", type=int, default=512,
+                    help="headline block length (the fastest of the configured sweep 128..1024)")
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
@@ -43,6 +44,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batched-tune", default=None,
+                    help="fixed batched shapes 'L:v:waves,...' per code instead of autotuning")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-pool", type=int, default=4096)
     ap.add_argument("--serve-arena-mb", type=int, default=256)
@@ -67,11 +70,13 @@ def traffic_from_profiles(kernel_tag):
 
 
 def source_hash():
+    """Hash of the sources that define the blocked decode kernel and its launch."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2011_09337_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        if f in ("vit_decoder.h", "vit_internal.h", "vit_launch.hip") or f.startswith("vit_kernels_k"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -169,16 +174,22 @@ def bench_batched(vit, torch, args):
     torch.cuda.synchronize()
     frames_np = vit.frames_array(frames)  # the frame list as the C ABI reads it
     b = vit.Batch()
-    tunes = b.autotune(codes, frames_np, q_d, out)
+    if args.batched_tune:
+        tunes = []
+        for t in args.batched_tune.split(","):
+            L_, v_, w_ = (int(x) for x in t.split(":"))
+            tunes.append((L_, v_, -1, w_))
+    else:
+        tunes = b.autotune(codes, frames_np, q_d, out)
     stream = torch.cuda.current_stream()
     for _ in range(2):
-        b.decode(codes, frames_np, q_d, out, stream=stream)
+        b.decode(codes, frames_np, q_d, out, tune=tunes, stream=stream)
     torch.cuda.synchronize()
     steps = max(3, args.steps // 2)
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record(stream)
     for _ in range(steps):
-        b.decode(codes, frames_np, q_d, out, stream=stream)
+        b.decode(codes, frames_np, q_d, out, tune=tunes, stream=stream)
     s1.record(stream)
     torch.cuda.synchronize()
     ms = s0.elapsed_time(s1) / steps

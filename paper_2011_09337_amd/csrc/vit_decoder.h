@@ -230,6 +230,7 @@ struct Decoder {
   int lane;
   int slot0;             // slot index of register 0 in this lane
   int xor32_addr;        // ds_bpermute byte address of lane ^ 32
+  uint32_t own_mask[REGS];  // per body offset: bit q of this slot's index (traceback encoding)
 
   // per-block state
   float o[REGS];
@@ -282,6 +283,18 @@ struct Decoder {
       const int bq = (st0 >> q) & 1, bqm = (st0 >> ((q + P - 1) % P)) & 1;
       sgn[q] = (bq ^ bqm) ? -1.0f : 1.0f;
       cmed[q] = bq ? -INFINITY : INFINITY;
+    }
+    // The survivor word of a slot stores, for body offset pos (bit BODY-1-pos),
+    // its decision XOR bit (pos mod P) of the slot index: following the
+    // survivor then flips that bit of the traceback's slot index instead of
+    // replacing it.
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int st = ((reg << 6) | slot0) & (S - 1);
+      uint32_t m = 0;
+#pragma unroll
+      for (int pos = 0; pos < BODY; ++pos) m |= (uint32_t)((st >> (pos % P)) & 1) << (BODY - 1 - pos);
+      own_mask[reg] = m;
     }
   }
 
@@ -392,7 +405,7 @@ struct Decoder {
 #pragma unroll
       for (int reg = 0; reg < REGS; ++reg) {
         flush_decision(dec[reg], pend[reg]);
-        lds[(body * REGS + reg) * 64 + slot0] = dec[reg];
+        lds[(body * REGS + reg) * 64 + slot0] = dec[reg] ^ own_mask[reg];
       }
     }
   }
@@ -424,6 +437,16 @@ struct Decoder {
     }
   }
 };
+
+// Register rsel (uniform) of a per-lane register array, without branches.
+template <int REGS>
+__device__ __forceinline__ uint32_t select_reg(const uint32_t (&v)[REGS], uint32_t rsel) {
+  typedef uint32_t vec_t __attribute__((ext_vector_type(REGS)));
+  vec_t t;
+#pragma unroll
+  for (int i = 0; i < REGS; ++i) t[i] = v[i];
+  return t[rsel & (REGS - 1)];
+}
 
 // The first (partial) body of a block: step G runs only from the entry offset
 // r on (uniform, scalar branches).  Later bodies run every step unguarded.
@@ -524,37 +547,42 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   }
 
   // ---- traceback (Algorithm 2) on the scalar unit.  lam is the slot index
-  // of the current state; the decision words are stored by slot, so its
-  // decision bit is bit (BODY-1-pos) of lane lam & 63 of register lam >> 6.
-  // Following the survivor replaces bit q = (body offset) mod (k-1) of the
-  // slot index with that decision bit.  The decision bit read at body offset
-  // g is the input bit of offset g - (k-1) (the oldest input of the state),
-  // so the decision stream, followed by the k-1 bits of the start slot, is
-  // the decoded sequence shifted by k-1: bit t of the output is stream bit
-  // (t - stage_base) + k - 1.  Each group's 32-bit stream word replaces the
-  // first decision dword of its group in LDS.
+  // of the current state.  Following the survivor at body offset pos replaces
+  // bit q = pos mod P of the slot index with the decision bit; the survivor
+  // words hold that bit XOR the slot's own bit q, so the step is
+  // lam ^= (word bit) << q.  Per group the words are bit-reversed and, per
+  // phase period p0..p0+P-1, shifted so that offset p0 + q sits at bit q:
+  // a step is one v_readlane and two scalar operations.  The decision bit at
+  // offset g is the input bit of offset g - (k-1) (the oldest input of the
+  // state), so the decision stream, followed by the k-1 bits of the start
+  // slot, is the decoded sequence shifted by k-1: bit t of the output is
+  // stream bit (t - stage_base) + k - 1.  Each group's stream word replaces
+  // the first survivor word of its group in LDS.
   const uint32_t lam_start = (uint32_t)lam;
   const int grp_lo = ((int)(cs - s) + r) / BODY;
+  uint32_t ulam = (uint32_t)lam;
   for (int grp = nbody - 1; grp >= grp_lo; --grp) {
     uint32_t dv[REGS];
 #pragma unroll
-    for (int rr = 0; rr < REGS; ++rr) dv[rr] = D.lds[(grp * REGS + rr) * 64 + D.lane];
+    for (int rr = 0; rr < REGS; ++rr) dv[rr] = __builtin_bitreverse32(D.lds[(grp * REGS + rr) * 64 + D.lane]);
     uint32_t acc = 0;
 #pragma unroll
-    for (int pos = BODY - 1; pos >= 0; --pos) {
-      const int q = pos % P;
-      uint32_t w = __builtin_amdgcn_readlane(dv[0], lam & 63);
+    for (int p0 = BODY - P; p0 >= 0; p0 -= P) {
+      uint32_t sh[REGS];
 #pragma unroll
-      for (int rr = 1; rr < REGS; ++rr)
-        if ((lam >> 6) == rr) w = __builtin_amdgcn_readlane(dv[rr], lam & 63);
-      // decision bit (BODY-1-pos) of w moved straight to bit q of the slot index
-      const int sh = BODY - 1 - pos - q;
-      const uint32_t dq = (sh >= 0 ? (w >> sh) : (w << -sh)) & (1u << q);
-      lam = (int)(((uint32_t)lam & ~(1u << q)) | dq);
-      // after the k-1 stages of a phase period, bit q of the slot index holds
-      // the decision of offset pos + q: the slot index is that period's slice
-      // of the decision stream
-      if (q == 0) acc |= ((uint32_t)lam & (uint32_t)(S - 1)) << pos;
+      for (int rr = 0; rr < REGS; ++rr) sh[rr] = dv[rr] >> (32 - BODY + p0);
+      uint32_t src = sh[0];
+#pragma unroll
+      for (int q = P - 1; q >= 0; --q) {
+        if constexpr (REGS > 1) {
+          // the register holding slot ulam is given by bits >= 6 of the slot
+          // index, which change only at q >= 6: select at q >= 5 only
+          if (q >= 5) src = select_reg<REGS>(sh, ulam >> 6);
+        }
+        const uint32_t w = __builtin_amdgcn_readlane(src, (int)(ulam & 63u));
+        ulam ^= w & (1u << q);
+      }
+      acc |= (ulam & (uint32_t)(S - 1)) << p0;
     }
     D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
   }
