@@ -26,7 +26,12 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded info Mbps on 1 MI355X (K=7 r1/2 and batched mixed) + % roofline, p99 latency"
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Peak of the add-compare-select operation mix (2 adds, 1 compare, 1 select
+# per state and stage = 4 lane-ops) on 256 CUs x 4 SIMDs at 2.4 GHz: adds at
+# the fp32 FMA rate (157.3 TFLOP/s: 2 cycles per wave64 instruction), compare
+# and select at half of it (4 cycles: v_cmp, v_max/v_med3, measured by
+# tests/microbench/valu_issue_rates.hip).  256 lane-ops per 12 cycles per SIMD.
+VALU_PEAK_TOPS = 256 * 4 * 2.4e9 * (4 * 64) / (2 * 2 + 4 + 4) / 1e12
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -98,20 +103,24 @@ def time_decode(vit, torch, code, llr_d, out_d, n, L, v, steps, warmup):
 
 def cpu_baseline(code_np, llr, n, L, v):
     """The oracle as it stands, on the host cores: all-core blocked decode of
-    the first 2^22 bits (terminated sample), and single-core on 2^19."""
+    the whole stream (best of 3 passes, about 10-30 core-seconds), and
+    single-core on its first 2^21 bits."""
     from oracle import vref
     import synth
     threads = len(os.sched_getaffinity(0))
     k, gens = synth.CODES["k7r12"]
     c = vref.make_code(k, list(gens))
     res = {}
-    for tag, nb, th in (("all", 1 << 22, threads), ("one", 1 << 19, 1)):
+    for tag, nb, th, reps in (("all", n, threads, 3), ("one", 1 << 21, 1, 1)):
         nb = min(nb, n)
         sub = llr[: (nb + k - 1) * 2]  # the first nb stages plus k-1 more as a tail
-        t0 = time.perf_counter()
-        vref.decode_blocked(c, sub, nb, L, v // 2, v - v // 2, True, nthreads=th)
-        dt = time.perf_counter() - t0
-        res[tag] = (nb / dt / 1e6, nb, dt, th)
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            vref.decode_blocked(c, sub, nb, L, v // 2, v - v // 2, True, nthreads=th)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        res[tag] = (nb / best / 1e6, nb, best, th)
     return res
 
 
@@ -440,7 +449,8 @@ def main():
         res = cpu_baseline(None, llr, n, args.L, v)
         mbps, nb, dt, th = res["all"]
         cpu = {"value": round(mbps, 3), "unit": "Mbps", "cores": th, "kind": "oracle",
-               "sample": f"first {nb} bits of the stream, blocked L={args.L} v={v}, {dt:.2f} s",
+               "sample": f"the whole {nb}-bit stream, blocked L={args.L} v={v}, best of 3 passes: {dt:.2f} s "
+                         f"on {th} threads; single-core figure on the first 2^21 bits",
                "single_core_mbps": round(res["one"][0], 3)}
     batched = None if args.no_batched else bench_batched(vit, torch, args)
     if batched:
