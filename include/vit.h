@@ -63,7 +63,10 @@ enum {
 };
 
 enum { VIT_TIE_LOWER_PRED = 0 };
-enum { VIT_LLR_F32 = 0, VIT_LLR_I8 = 1 };
+/* Soft-input types.  VIT_LLR_HARD: hard decisions, one byte per coded bit,
+ * 0 for coded bit 0 and any other value for coded bit 1, decoded as integer
+ * LLRs +1 / -1 (the hard-decision mode of Sec. I and II-C). */
+enum { VIT_LLR_F32 = 0, VIT_LLR_I8 = 1, VIT_LLR_HARD = 2 };
 
 /* A (beta,1,k) code: 3 <= k <= 9, 2 <= beta <= 4, 0 < gen[b] < 2^k. */
 typedef struct {
@@ -75,7 +78,7 @@ typedef struct {
 /* Options of vit_decode_ex.  Fill with vit_opts_default() and set size. */
 typedef struct {
   uint32_t size;         /* sizeof(vit_opts)                                     */
-  int32_t llr_type;      /* VIT_LLR_F32 (float) or VIT_LLR_I8 (int8, see below)  */
+  int32_t llr_type;      /* VIT_LLR_F32 (float), VIT_LLR_I8 (int8) or VIT_LLR_HARD */
   int32_t terminated;    /* 1: the stream carries k-1 tail stages (default 1)    */
   int32_t v1;            /* left overlap; -1 = floor(v/2) (default -1)           */
   int32_t check_finite;  /* reserved, must be 0                                  */
@@ -98,7 +101,9 @@ int vit_decode(const vit_code *code, const float *llr, int64_t n, int32_t L, int
  * work is queued; kernel faults surface at the caller's next synchronisation.
  * With llr_type = VIT_LLR_I8 the LLRs are int8 values (any range, -128
  * allowed) and the decoder computes exactly in integers: decisions are those
- * of exact arithmetic on the int8 values.  opts may be NULL (defaults). */
+ * of exact arithmetic on the int8 values.  With VIT_LLR_HARD the input is one
+ * byte per coded bit (0 / nonzero) decoded as the integer LLRs +1 / -1.
+ * opts may be NULL (defaults). */
 int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v,
                   int32_t tie_rule, uint8_t *out_bits, const vit_opts *opts);
 
@@ -169,7 +174,8 @@ int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_fr
                              const vit_tuning *tune, size_t *bytes);
 
 /* Decode a batch.  codes: ncodes (1..8) codes; frames: host array; llr: device
- * buffer of llr_count elements of llr_type; out: device buffer of out_bytes
+ * buffer of llr_count elements of llr_type (VIT_LLR_F32, VIT_LLR_I8 or
+ * VIT_LLR_HARD); out: device buffer of out_bytes
  * bytes (frames' output ranges must not overlap); tune: one vit_tuning per
  * code, or NULL for the plan's autotuned shapes (default L = 256, v = 5k,
  * 1 wave per workgroup when not tuned); workspace: device memory of at least
@@ -214,7 +220,7 @@ typedef struct vit_server vit_server;
 
 typedef struct {
   uint32_t size;             /* sizeof(vit_server_config)                           */
-  int32_t llr_type;          /* VIT_LLR_I8 or VIT_LLR_F32, for every request         */
+  int32_t llr_type;          /* VIT_LLR_I8, VIT_LLR_F32 or VIT_LLR_HARD, every request */
   int32_t max_frames;        /* frames admitted to the device at once (slots), >= 1  */
   int32_t max_items;         /* blocks per iteration, >= 1                           */
   int32_t max_pending;       /* queued requests beyond which submit says VIT_EBUSY   */

@@ -11,7 +11,7 @@ from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_ba
 from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
                    vit_server_workspace_size)
-from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_I8, VIT_OK,
+from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_HARD, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
 
@@ -19,15 +19,15 @@ __all__ = ["decode", "quantize", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYP
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
-           "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8",
+           "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8", "VIT_LLR_HARD",
            "VIT_TIE_LOWER_PRED"]
 
 
 def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
-    values, time-major).  Returns (or fills) a uint8 device tensor of
-    ceil(n/8) packed bytes.  Asynchronous on `stream` (default: torch's
-    current stream)."""
+    values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
+    Returns (or fills) a uint8 device tensor of ceil(n/8) packed bytes.
+    Asynchronous on `stream` (default: torch's current stream)."""
     import torch
 
     if not llr.is_cuda or not llr.is_contiguous():
@@ -36,8 +36,10 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=Non
         llr_type = VIT_LLR_F32
     elif llr.dtype == torch.int8:
         llr_type = VIT_LLR_I8
+    elif llr.dtype == torch.uint8:
+        llr_type = VIT_LLR_HARD
     else:
-        raise TypeError(f"llr dtype {llr.dtype} (float32 or int8 expected)")
+        raise TypeError(f"llr dtype {llr.dtype} (float32, int8 or uint8 hard decisions expected)")
     nbytes = (int(n) + 7) // 8
     if out is None:
         out = torch.empty(nbytes, dtype=torch.uint8, device=llr.device)
@@ -109,7 +111,7 @@ class Batch:
         codes_arr, frames_arr = codes_array(codes), frames_array(frames)
         tune_arr = tunings_array(tune) if tune is not None else None
         ws, ws_bytes = self._workspace(codes_arr, frames_arr, tune_arr)
-        llr_type = VIT_LLR_I8 if llr.dtype == torch.int8 else VIT_LLR_F32
+        llr_type = {torch.int8: VIT_LLR_I8, torch.uint8: VIT_LLR_HARD}.get(llr.dtype, VIT_LLR_F32)
         if stream is None:
             stream = torch.cuda.current_stream(llr.device)
         vit_decode_batch(self.plan, codes_arr, frames_arr, llr.data_ptr(), llr.numel(), llr_type, out.data_ptr(),
@@ -120,7 +122,7 @@ class Batch:
         import torch
         codes_arr, frames_arr = codes_array(codes), frames_array(frames)
         ws, ws_bytes = self._workspace(codes_arr, frames_arr, None)
-        llr_type = VIT_LLR_I8 if llr.dtype == torch.int8 else VIT_LLR_F32
+        llr_type = {torch.int8: VIT_LLR_I8, torch.uint8: VIT_LLR_HARD}.get(llr.dtype, VIT_LLR_F32)
         if stream is None:
             stream = torch.cuda.current_stream(llr.device)
         return vit_plan_autotune(self.plan, codes_arr, frames_arr, llr.data_ptr(), llr.numel(), llr_type,

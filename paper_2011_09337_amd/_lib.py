@@ -20,6 +20,7 @@ VIT_EBUSY = -5
 VIT_TIE_LOWER_PRED = 0
 VIT_LLR_F32 = 0
 VIT_LLR_I8 = 1
+VIT_LLR_HARD = 2
 
 STATUS_NAMES = {VIT_OK: "VIT_OK", VIT_EINVAL: "VIT_EINVAL", VIT_EUNSUPPORTED: "VIT_EUNSUPPORTED",
                 VIT_ENOMEM: "VIT_ENOMEM", VIT_EDEVICE: "VIT_EDEVICE", VIT_EBUSY: "VIT_EBUSY"}

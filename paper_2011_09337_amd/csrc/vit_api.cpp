@@ -155,18 +155,18 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   if (tie_rule != VIT_TIE_LOWER_PRED) return fail(VIT_EINVAL, "unknown tie rule %d", tie_rule);
   if (!llr) return fail(VIT_EINVAL, "llr is NULL");
   if (!out_bits) return fail(VIT_EINVAL, "out_bits is NULL");
-  if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8) return fail(VIT_EINVAL, "unknown llr_type %d",
-                                                                         o.llr_type);
+  if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8 && o.llr_type != VIT_LLR_HARD)
+    return fail(VIT_EINVAL, "unknown llr_type %d", o.llr_type);
   if (o.check_finite != 0) return fail(VIT_EUNSUPPORTED, "check_finite is not implemented");
   Geometry g;
   int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
   if (st) return st;
   if (L > 0 && (L % 8) != 0) return fail(VIT_EUNSUPPORTED, "L = %d must be a multiple of 8", L);
   // the kernels address LLRs with 32-bit byte offsets inside the stream
-  const int64_t llr_bytes = g.N * code->beta * (o.llr_type == VIT_LLR_I8 ? 1 : 4);
+  const int64_t llr_bytes = g.N * code->beta * (o.llr_type == VIT_LLR_F32 ? 4 : 1);
   if (llr_bytes >= ((int64_t)1 << 32) || g.N >= ((int64_t)1 << 31))
     return fail(VIT_EUNSUPPORTED, "stream of %lld LLR bytes is too long (limit 2^32)", (long long)llr_bytes);
-  if (o.llr_type == VIT_LLR_I8) {
+  if (o.llr_type != VIT_LLR_F32) {
     // integer metrics are exact in fp32 while |metric| < 2^24
     const int64_t bound = g.max_block_stages * 128 * code->beta;
     if (bound >= ((int64_t)1 << 24))

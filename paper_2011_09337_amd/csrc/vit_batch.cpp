@@ -185,7 +185,7 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
 
 int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes, int64_t llr_count,
                  int llr_type, int64_t out_bytes, std::vector<std::pair<int64_t, int64_t>> &outs) {
-  const int elem = llr_type == VIT_LLR_I8 ? 1 : 4;
+  const int elem = llr_type == VIT_LLR_F32 ? 4 : 1;
   outs.clear();
   outs.reserve(nframes);
   for (int32_t f = 0; f < nframes; ++f) {
@@ -319,14 +319,15 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
   if (st) return st;
   if (!llr || !out || !workspace) return api_fail(VIT_EINVAL, "NULL buffer");
   if (((uintptr_t)workspace & 255u) != 0) return api_fail(VIT_EINVAL, "workspace must be 256-byte aligned");
-  if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8) return api_fail(VIT_EINVAL, "unknown llr_type %d", llr_type);
+  if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8 && llr_type != VIT_LLR_HARD)
+    return api_fail(VIT_EINVAL, "unknown llr_type %d", llr_type);
   st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges);
   if (st) return st;
   vit_tuning shape[kMaxCodes];
   st = resolve_shapes(plan, codes, ncodes, frames, nframes, llr_type, tune, shape);
   if (st) return st;
 
-  const int elem = llr_type == VIT_LLR_I8 ? 1 : 4;
+  const int elem = llr_type == VIT_LLR_F32 ? 4 : 1;
   const int64_t total = build_items(codes, ncodes, frames, nframes, shape, elem, nullptr, nullptr, nullptr);
   const size_t need = kHeaderBytes + (size_t)total * sizeof(WorkItem);
   if (workspace_bytes < need)
@@ -355,7 +356,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
   if (he != hipSuccess) return vit::api_fail_hip(he, "hipGetDevice");
 
   for (int c = 0; c < ncodes; ++c)
-    if (llr_type == VIT_LLR_I8 && ((int64_t)shape[c].L + shape[c].v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
+    if (llr_type != VIT_LLR_F32 && ((int64_t)shape[c].L + shape[c].v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
       return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
 
   // graph: reuse while buffers, codes and shapes are unchanged
@@ -379,7 +380,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     for (int c = 0; c < ncodes; ++c) {
       int unsupported = 0;
       const char *why = "";
-      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type == VIT_LLR_I8,
+      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type != VIT_LLR_F32,
                                   (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &bl[c], &unsupported,
                                   &why);
       if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
@@ -398,6 +399,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
       args.header = (int32_t *)workspace;
       args.items = (const WorkItem *)((char *)workspace + kHeaderBytes);
       args.code_index = c;
+      args.hard = llr_type == VIT_LLR_HARD ? 1 : 0;
       for (int b = 0; b < 4; ++b) args.gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0u;
       int words = bl[c].lds_words_per_wave;
       void *kargs[] = {&args, &words};

@@ -231,6 +231,7 @@ struct Decoder {
   float bsign[BETA];     // signs of this lane's output pattern in the metric table
   int tl;                // stage of this lane's metric table entry within a tile
   int lane;
+  bool hard;             // byte inputs are hard decisions (0 / nonzero), not int8 LLRs
   int slot0;             // slot index of register 0 in this lane
   int xor32_addr;        // ds_bpermute byte address of lane ^ 32
   uint32_t own_mask[REGS];  // per body offset: bit q of this slot's index (traceback encoding)
@@ -330,8 +331,12 @@ struct Decoder {
   // eq. (2) for output pattern `pat` of this lane: sum in order b = 0..beta-1;
   // fma with a +-1 multiplier rounds exactly like the plain add.
   __device__ __forceinline__ float llr_value(int raw) const {
-    if constexpr (I8) return (float)raw;  // exact: |int8| <= 128
-    else return __builtin_bit_cast(float, raw);
+    if constexpr (I8) {
+      if (hard) return raw == 0 ? 1.0f : -1.0f;  // hard decision: coded bit 0 -> +1, 1 -> -1
+      return (float)raw;                         // exact: |int8| <= 128
+    } else {
+      return __builtin_bit_cast(float, raw);
+    }
   }
 
   template <int BUF>
@@ -642,6 +647,7 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
 
   Dec D;
   D.setup(a.gen);
+  D.hard = a.llr_type == VIT_LLR_HARD;
   // wave index and count are uniform across the wave: keep them scalar
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
@@ -690,6 +696,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
   extern __shared__ uint32_t vit_lds[];
   Dec D;
   D.setup(a.gen);
+  D.hard = a.hard != 0;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
   D.lds = vit_lds + (size_t)wid * lds_words_per_wave;

@@ -22,7 +22,7 @@ struct DecodeArgs {
   uint32_t gen[4];
   int32_t k, beta;
   int32_t terminated;
-  int32_t llr_type;      // VIT_LLR_F32 or VIT_LLR_I8
+  int32_t llr_type;      // VIT_LLR_F32, VIT_LLR_I8 or VIT_LLR_HARD
   int32_t max_block_stages;
 };
 
@@ -49,6 +49,7 @@ struct BatchArgs {
   int32_t *header;           // device, workspace header
   const WorkItem *items;     // device, all work items (each code's run is cost-descending)
   int32_t code_index;
+  int32_t hard;              // 1: one byte per coded bit, 0 / nonzero -> LLR +1 / -1
   uint32_t gen[4];
 };
 

@@ -45,7 +45,7 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   *unsupported = 0;
   bool stdc = true;
   for (int b = 0; b < a.beta; ++b) stdc = stdc && ((a.gen[b] >> (a.k - 1)) & 1u) && (a.gen[b] & 1u);
-  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type == 1);
+  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type != VIT_LLR_F32);
   if (!fn) {
     *unsupported = 1;
     *why = "no kernel instance for this (k, beta)";

@@ -57,7 +57,7 @@ int check_config(const vit_server_config *cfg) {
   if (!cfg) return api_fail(VIT_EINVAL, "config is NULL");
   if (cfg->size != sizeof(vit_server_config))
     return api_fail(VIT_EINVAL, "config size %u, expected %zu", cfg->size, sizeof(vit_server_config));
-  if (cfg->llr_type != VIT_LLR_F32 && cfg->llr_type != VIT_LLR_I8)
+  if (cfg->llr_type != VIT_LLR_F32 && cfg->llr_type != VIT_LLR_I8 && cfg->llr_type != VIT_LLR_HARD)
     return api_fail(VIT_EINVAL, "unknown llr_type %d", cfg->llr_type);
   if (cfg->max_frames < 1 || cfg->max_frames > (1 << 20))
     return api_fail(VIT_EINVAL, "max_frames = %d outside [1, 2^20]", cfg->max_frames);
@@ -196,6 +196,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     a.header = (int32_t *)wsd;
     a.items = (const vit::WorkItem *)(wsd + kHeaderBytes);
     a.code_index = c;
+    a.hard = s->llr_type == VIT_LLR_HARD ? 1 : 0;
     for (int b = 0; b < 4; ++b) a.gen[b] = b < s->codes[c].beta ? s->codes[c].gen[b] : 0u;
     int words = s->bl[c].lds_words_per_wave;
     void *kargs[] = {&a, &words};
@@ -380,7 +381,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
     if (t.v < 0 || t.v1 < -1 || t.v1 > t.v) return api_fail(VIT_EINVAL, "code %d: bad overlap (v %d, v1 %d)", c, t.v, t.v1);
     if (t.waves_per_block < 1 || t.waves_per_block > 4)
       return api_fail(VIT_EINVAL, "code %d: waves_per_block = %d outside [1, 4]", c, t.waves_per_block);
-    if (cfg->llr_type == VIT_LLR_I8 && ((int64_t)t.L + t.v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
+    if (cfg->llr_type != VIT_LLR_F32 && ((int64_t)t.L + t.v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
       return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
   }
   if (!cfg->arena || !cfg->workspace || !cfg->host) return api_fail(VIT_EINVAL, "NULL arena, workspace or host region");
@@ -414,7 +415,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
   if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostGetDevicePointer"));
   s->stream = (hipStream_t)cfg->stream;
   s->llr_type = cfg->llr_type;
-  s->elem = cfg->llr_type == VIT_LLR_I8 ? 1 : 4;
+  s->elem = cfg->llr_type == VIT_LLR_F32 ? 4 : 1;
   s->ncodes = ncodes;
   s->arena = (uint8_t *)cfg->arena;
   s->arena_bytes = cfg->arena_bytes;
@@ -432,7 +433,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
     s->shape[c] = shape[c];
     int unsupported = 0;
     const char *why = "";
-    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type == VIT_LLR_I8,
+    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type != VIT_LLR_F32,
                                (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &s->bl[c], &unsupported,
                                &why);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "batch launch planning"));

@@ -75,6 +75,11 @@ def make_stream(code_name, n, ebn0_db, seed, terminated=True):
     return bits, llr
 
 
+def hard_bits(llr):
+    """Hard decisions of soft inputs: coded bit 1 where the LLR is negative."""
+    return (np.asarray(llr) < 0).astype(np.uint8)
+
+
 def integer_llr(num, lo, hi, rng):
     """Small integer-valued LLRs (float32): exact sums, many ties."""
     return rng.integers(lo, hi + 1, size=int(num)).astype(np.float32)

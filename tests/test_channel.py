@@ -73,3 +73,31 @@ def test_ber_falls_with_ebn0_and_blocked_gap_shrinks_with_v2():
             assert np.mean(outs[3] != bits) < 1.25 * bers[-1]
     assert bers[0] > bers[1] > bers[2]
     assert bers[1] < _q(math.sqrt(10 ** 0.2))  # coding gain over the raw channel
+
+
+def test_hard_decision_costs_about_two_db():
+    # Soft inputs are worth about 2 dB over hard decisions for this code
+    # (Sec. I and II-C).  The hard-decision decoder is the same decoder on
+    # integer LLRs +1 / -1 (coded bit 0 / 1).  Statistical, on 2^17 bits: find
+    # the Eb/N0 at which hard decisions reach the soft-input BER at 2 dB, by
+    # log-linear interpolation.
+    k, gens = synth.CODES["k7r12"]
+    c = vref.make_code(k, list(gens))
+    n = 1 << 17
+
+    def ber(ebn0, hard):
+        bits, llr = synth.make_stream("k7r12", n, ebn0, seed=31)
+        if hard:
+            llr = np.where(synth.hard_bits(llr) != 0, -1, 1).astype(np.int8)
+        return float(np.mean(vref.decode_full(c, llr, n, True) != bits))
+
+    target = ber(2.0, False)
+    grid = (3.5, 4.0, 4.5)
+    hard = [ber(e, True) for e in grid]
+    assert hard[0] > hard[1] > hard[2]
+    assert hard[0] > target > hard[2]
+    i = 0 if hard[1] < target else 1
+    x0, x1 = grid[i], grid[i + 1]
+    y0, y1 = math.log(hard[i]), math.log(hard[i + 1])
+    gap = x0 + (math.log(target) - y0) * (x1 - x0) / (y1 - y0) - 2.0
+    assert 1.5 < gap < 3.0, gap

@@ -93,6 +93,18 @@ def test_batch_mixed_codes_matches_oracle(dev, int8):
     b.close()
 
 
+def test_batch_hard_decisions_match_oracle(dev):
+    # hard-decision frames (one byte per coded bit) against the oracle on +1 / -1
+    torch, vit = dev
+    rng = np.random.default_rng(19)
+    frames, llr, out_bytes, _ = make_batch(rng, 120, [0, 1, 2, 3, 4], 1, 1500)
+    hard = synth.hard_bits(llr)
+    b = vit.Batch()
+    got = run_batch(dev, b, frames, hard, out_bytes, None, TUNE)
+    check_frames(got, frames, np.where(hard != 0, -1, 1).astype(np.int8), TUNE)
+    b.close()
+
+
 def test_batch_equals_frames_alone(dev):
     torch, vit = dev
     rng = np.random.default_rng(3)

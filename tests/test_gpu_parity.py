@@ -162,6 +162,26 @@ def test_int8_llrs_exact(dev, name):
 
 # ----------------------------------------------------------------------------- many blocks
 
+@pytest.mark.parametrize("name", ["k7r12", "k7r13", "k9r12", "k4r14", "k5r12x"])
+def test_hard_decisions_exact(dev, name):
+    # hard-decision input (one byte per coded bit, 0 / nonzero) against the
+    # oracle on the integer LLRs +1 / -1; nonzero bytes other than 1 included
+    k, gens = CODES[name]
+    n = 3000
+    bits, llr = synth.make_stream(name, n, 3.0, seed=17) if name in synth.CODES else (None, None)
+    if llr is None:
+        rng = np.random.default_rng(17)
+        coded = synth.encode(k, gens, synth.info_bits(n, rng), True)
+        llr = synth.awgn_llr(coded, 3.0, len(gens), rng)
+    hard = synth.hard_bits(llr)
+    hard[hard != 0] = np.random.default_rng(3).integers(1, 256, size=int(np.sum(hard != 0)), dtype=np.uint8)
+    q = np.where(hard != 0, -1, 1).astype(np.int8)
+    for L, v in ((0, 0), (64, 35), (256, 45)):
+        got = _gpu(dev, k, gens, hard, n, L, v)
+        want = _oracle(k, gens, q, n, L, v)
+        np.testing.assert_array_equal(got, want)
+
+
 @pytest.mark.parametrize("L", [128, 256, 512, 1024])
 def test_many_blocks_k7(dev, L):
     # 2^21 bits: more blocks than resident waves, so each wave loops over
