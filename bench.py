@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--table2", action="store_true",
+                    help="only the BER-gap sweep over f (=L) x v2 (the paper's Table II grid), then exit")
     ap.add_argument("--batched-tune", default=None,
                     help="fixed batched shapes 'L:v:waves,...' per code instead of autotuning")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -386,6 +388,69 @@ def bench_serving(vit, torch, args, tunes):
     }
 
 
+def ber_gap_sweep(vit, torch, log2n=24):
+    """Eb/N0 gap at BER 1e-4 between the blocked decoder and maximum-likelihood
+    decoding, over the paper's Table II grid (f = L in {32..512}, v2 in
+    {10..40}; v1 = v2), K=7 r1/2, FP32 LLRs, 2^log2n bits per Eb/N0 point.
+    The ML reference is the blocked decoder with v1 = v2 = 128 (traceback
+    depth far beyond convergence); the oracle's full-frame ML checks it on the
+    first 2^18 bits of every point."""
+    import numpy as np
+    import synth
+    from oracle import vref
+    k, gens = synth.CODES["k7r12"]
+    code = vit.make_code(k, gens)
+    ocode = vref.make_code(k, list(gens))
+    n = 1 << log2n
+    grid = [2.5, 3.0, 3.5, 4.0, 4.5, 5.0]
+    fs, v2s = (32, 64, 128, 256, 512), (10, 20, 30, 40)
+    errs = {}
+    ml_check = []
+    out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
+    for e in grid:
+        bits, llr = synth.make_stream("k7r12", n, e, seed=100 + int(e * 10))
+        d = torch.from_numpy(llr).cuda()
+
+        def nerr(L, v1, v2):
+            vit.decode(code, d, n, L, v1 + v2, v1=v1, out=out)
+            got = synth.unpack_bits(out.cpu().numpy(), n)
+            return int(np.sum(got != bits)), got
+
+        ml_e, ml_bits = nerr(512, 128, 128)
+        errs[("ml", e)] = ml_e
+        # the oracle's full-frame ML on the first m stages as an open stream;
+        # its last bits depend on the unknown end state, so they are not compared
+        m = 1 << 18
+        ref = vref.decode_full(ocode, llr[: m * 2], m, terminated=False)
+        ml_check.append(int(np.sum(ref[: m - 64] != ml_bits[: m - 64])))
+        for f in fs:
+            for v2 in v2s:
+                errs[(f, v2, e)] = nerr(f, v2, v2)[0]
+
+    def ebn0_at(key_of):
+        bers = [max(errs[key_of(e)], 0.5) / n for e in grid]
+        for i in range(len(grid) - 1):
+            if bers[i] >= 1e-4 > bers[i + 1]:
+                y0, y1 = np.log(bers[i]), np.log(bers[i + 1])
+                return grid[i] + (np.log(1e-4) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
+        return None
+
+    ml_at = ebn0_at(lambda e: ("ml", e))
+    table = {}
+    for v2 in v2s:
+        for f in fs:
+            at = ebn0_at(lambda e, f=f, v2=v2: (f, v2, e))
+            table[f"v2={v2},f={f}"] = None if at is None or ml_at is None else round(float(at - ml_at), 4)
+    return {
+        "workload": f"K=7 r1/2, FP32 LLRs, 2^{log2n} bits per point, Eb/N0 {grid[0]}..{grid[-1]} dB; v1 = v2; "
+                    f"gap = Eb/N0 at BER 1e-4 minus that of the ML reference (v1 = v2 = 128)",
+        "ml_ebn0_at_1e-4": None if ml_at is None else round(float(ml_at), 4),
+        "ml_errors": {str(e): errs[("ml", e)] for e in grid},
+        "ml_reference_vs_full_frame_ml_bit_differences": ml_check,
+        "gap_db": table,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -397,6 +462,10 @@ def main():
 
     import paper_2011_09337_amd as vit
     import synth
+
+    if args.table2:
+        print(json.dumps({"table2": ber_gap_sweep(vit, torch)}), flush=True)
+        return
 
     k, gens = synth.CODES["k7r12"]
     v = 5 * k
