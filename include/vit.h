@@ -116,6 +116,18 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
  * positive and finite; VIT_EDEVICE for launch failures. */
 int vit_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q, void *stream);
 
+/* De-puncturing (Sec. IV-E): expand a punctured stream of soft inputs into
+ * `stages` stages of beta values, with a zero LLR in every punctured slot, for
+ * the decoders above.  mask (host, period*beta bytes, period*beta <= 64):
+ * mask[p*beta + b] != 0 if output b of a stage t with t mod period = p is
+ * transmitted.  received (device) holds the transmitted values in stream
+ * order, exactly as many as the pattern keeps in `stages` stages; out
+ * (device) receives stages*beta values.  llr_type VIT_LLR_F32 or VIT_LLR_I8.
+ * Asynchronous on `stream`.  Errors: VIT_EINVAL for a bad pattern, count or
+ * buffer; VIT_EDEVICE for launch failures. */
+int vit_depuncture(const void *received, int64_t received_count, int32_t llr_type, const uint8_t *mask,
+                   int32_t period, int32_t beta, int64_t stages, void *out, void *stream);
+
 /* Default options: FP32, terminated, v1 = floor(v/2), default stream. */
 vit_opts vit_opts_default(void);
 

@@ -237,6 +237,30 @@ int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q) {
   return 0;
 }
 
+/* De-puncturing (Sec. IV-E): walk the output stream stage by stage and slot
+ * by slot; a slot the pattern keeps takes the next received value, a
+ * punctured slot gets a zero LLR (no information). */
+#define DEFINE_DEPUNCTURE(NAME, T)                                                  \
+  int NAME(const T *in, int64_t in_count, const uint8_t *mask, int32_t period,     \
+           int32_t beta, int64_t stages, T *out) {                                 \
+    if (period < 1 || beta < 1 || stages < 0 || !mask || (stages > 0 && !out))      \
+      return -1;                                                                    \
+    int64_t used = 0;                                                               \
+    for (int64_t t = 0; t < stages; ++t) {                                          \
+      for (int32_t b = 0; b < beta; ++b) {                                          \
+        if (mask[(t % period) * beta + b]) {                                        \
+          if (used >= in_count) return -1;                                          \
+          out[t * beta + b] = in[used++];                                           \
+        } else {                                                                    \
+          out[t * beta + b] = (T)0;                                                 \
+        }                                                                           \
+      }                                                                             \
+    }                                                                               \
+    return used == in_count ? 0 : -1;                                               \
+  }
+DEFINE_DEPUNCTURE(vref_depuncture_f32, float)
+DEFINE_DEPUNCTURE(vref_depuncture_i8, int8_t)
+
 /* Exhaustive search (see vref.h).  x[] holds the k-1 prehistory inputs
  * followed by the window inputs, oldest first; the register of window stage
  * t' is built from x[t'] .. x[t'+k-1] with the newest input in bit k-1. */

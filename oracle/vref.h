@@ -86,6 +86,16 @@ int vref_window_f64(const vref_code *code, const double *llr, int64_t s, int64_t
 /* Saturating int8 quantiser: q = clamp(round_half_even(llr * scale), -127, 127). */
 int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q);
 
+/* De-puncturing (Sec. IV-E): expand a punctured stream into `stages` stages
+ * of beta LLRs.  mask[p*beta + b] != 0 when output b of stage t with
+ * t mod period = p was transmitted; transmitted values are taken from `in`
+ * in stream order, punctured slots get 0.  Returns 0, or -1 if in_count is
+ * not exactly the number of transmitted slots. */
+int vref_depuncture_f32(const float *in, int64_t in_count, const uint8_t *mask, int32_t period, int32_t beta,
+                        int64_t stages, float *out);
+int vref_depuncture_i8(const int8_t *in, int64_t in_count, const uint8_t *mask, int32_t period, int32_t beta,
+                       int64_t stages, int8_t *out);
+
 /* Exhaustive search over every input sequence of a window, for small windows
  * only (prehistory + window inputs <= 24 bits).  The window covers stages
  * [s, e) of an LLR stream; the k-1 inputs before stage s are free unless

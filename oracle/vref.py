@@ -52,9 +52,12 @@ def _declare(L):
     L.vref_window_f64.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, i64, i64, _P, _P]
     L.vref_quantize_i8.argtypes = [_P, i64, C.c_float, _P]
     L.vref_bruteforce_window.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, _P, _P]
+    L.vref_depuncture_f32.argtypes = [_P, i64, _P, i32, i32, i64, _P]
+    L.vref_depuncture_i8.argtypes = [_P, i64, _P, i32, i32, i64, _P]
     for fn in (L.vref_encode, L.vref_decode_full_f32, L.vref_decode_full_f64, L.vref_decode_full_i8,
                L.vref_decode_blocked_f32, L.vref_decode_blocked_f64, L.vref_decode_blocked_i8,
-               L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window):
+               L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window, L.vref_depuncture_f32,
+               L.vref_depuncture_i8):
         fn.restype = C.c_int
 
 
@@ -156,3 +159,15 @@ def bruteforce_window(code, llr, s, e, start_known, end_zero):
     _check(lib().vref_bruteforce_window(C.byref(code), _ptr(llr), s, e, int(start_known), int(end_zero),
                                         _ptr(out), C.byref(met)), "vref_bruteforce_window")
     return out, met.value
+
+
+def depuncture(received, mask, stages):
+    """De-puncturing (Sec. IV-E): mask is a (period, beta) 0/1 array; returns
+    stages*beta values with zeros in the punctured slots."""
+    received = np.ascontiguousarray(received)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    period, beta = mask.shape
+    out = np.zeros(stages * beta, dtype=received.dtype)
+    fn = {np.dtype(np.float32): lib().vref_depuncture_f32, np.dtype(np.int8): lib().vref_depuncture_i8}[received.dtype]
+    _check(fn(_ptr(received), received.size, _ptr(mask), period, beta, stages, _ptr(out)), fn.__name__)
+    return out

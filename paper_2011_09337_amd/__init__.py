@@ -13,9 +13,9 @@ from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_d
                    vit_server_workspace_size)
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_HARD, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
-                   vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry)
+                   vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry, vit_depuncture)
 
-__all__ = ["decode", "quantize", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
+__all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
@@ -70,6 +70,29 @@ def quantize(llr, scale, *, out=None, stream=None):
     if stream is None:
         stream = torch.cuda.current_stream(llr.device)
     vit_quantize_i8(llr.data_ptr(), llr.numel(), float(scale), out.data_ptr(), stream.cuda_stream)
+    return out
+
+
+def depuncture(received, mask, stages, *, out=None, stream=None):
+    """De-puncture a device tensor (float32 or int8) of transmitted values with
+    a (period, beta) 0/1 pattern (see vit_depuncture); returns stages*beta
+    values with zeros in the punctured slots."""
+    import numpy as np
+    import torch
+
+    mask = np.asarray(mask, dtype=np.uint8)
+    period, beta = mask.shape
+    if not received.is_cuda or not received.is_contiguous():
+        raise ValueError("received must be a contiguous device tensor")
+    llr_type = VIT_LLR_F32 if received.dtype == torch.float32 else VIT_LLR_I8
+    if received.dtype not in (torch.float32, torch.int8):
+        raise TypeError(f"received dtype {received.dtype} (float32 or int8 expected)")
+    if out is None:
+        out = torch.empty(int(stages) * beta, dtype=received.dtype, device=received.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(received.device)
+    vit_depuncture(received.data_ptr(), received.numel(), llr_type, mask.reshape(-1).tolist(), period, beta,
+                   int(stages), out.data_ptr(), stream.cuda_stream)
     return out
 
 

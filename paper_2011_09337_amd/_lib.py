@@ -99,6 +99,8 @@ lib.vit_query_geometry.argtypes = [C.POINTER(vit_code), C.c_int64, C.c_int32, C.
                                    C.POINTER(vit_geometry)]
 lib.vit_query_geometry.restype = C.c_int
 lib.vit_quantize_i8.argtypes = [_P, C.c_int64, C.c_float, _P, _P]
+lib.vit_depuncture.argtypes = [_P, C.c_int64, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int64, _P, _P]
+lib.vit_depuncture.restype = C.c_int
 lib.vit_quantize_i8.restype = C.c_int
 _PC = C.POINTER(vit_code)
 _PF = C.POINTER(vit_frame)
@@ -176,6 +178,12 @@ def vit_decode_ex(code, llr_ptr, n, L, v, tie_rule, out_ptr, opts=None):
 
 def vit_quantize_i8(llr_ptr, count, scale, q_ptr, stream=None):
     return _check(lib.vit_quantize_i8(llr_ptr, count, scale, q_ptr, stream))
+
+
+def vit_depuncture(received_ptr, received_count, llr_type, mask, period, beta, stages, out_ptr, stream=None):
+    m = (C.c_uint8 * (period * beta))(*[1 if x else 0 for x in mask])
+    return _check(lib.vit_depuncture(received_ptr, received_count, llr_type, m, period, beta, stages, out_ptr,
+                                     stream))
 
 
 def vit_query_geometry(code, n, L, v, v1=-1, terminated=1):

@@ -196,6 +196,36 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   return VIT_OK;
 }
 
+int vit_depuncture(const void *received, int64_t received_count, int32_t llr_type, const uint8_t *mask,
+                   int32_t period, int32_t beta, int64_t stages, void *out, void *stream) {
+  t_err[0] = 0;
+  if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8) return fail(VIT_EINVAL, "llr_type %d (F32 or I8)", llr_type);
+  if (!mask) return fail(VIT_EINVAL, "mask is NULL");
+  if (beta < 2 || beta > 4) return fail(VIT_EINVAL, "beta = %d outside [2, 4]", beta);
+  if (period < 1 || period * beta > 64) return fail(VIT_EINVAL, "period x beta = %d x %d outside [1, 64]", period, beta);
+  if (stages < 0 || received_count < 0) return fail(VIT_EINVAL, "negative size");
+  uint64_t bits = 0;
+  int32_t kept = 0;
+  for (int i = 0; i < period * beta; ++i)
+    if (mask[i]) {
+      bits |= 1ull << i;
+      ++kept;
+    }
+  if (kept == 0) return fail(VIT_EINVAL, "the pattern keeps no output");
+  // received values: whole periods, then the kept slots of the partial period
+  const int64_t whole = stages / period;
+  int64_t expect = whole * kept;
+  for (int i = 0; i < (int)(stages - whole * period) * beta; ++i) expect += mask[i] ? 1 : 0;
+  if (expect != received_count)
+    return fail(VIT_EINVAL, "%lld received values, the pattern keeps %lld in %lld stages", (long long)received_count,
+                (long long)expect, (long long)stages);
+  if (stages > 0 && (!received || !out)) return fail(VIT_EINVAL, "NULL buffer");
+  if (stages * beta >= ((int64_t)1 << 40)) return fail(VIT_EUNSUPPORTED, "stream too long");
+  hipError_t e = vit::launch_depuncture(received, llr_type, bits, period, beta, kept, stages, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "depuncture launch");
+  return VIT_OK;
+}
+
 int vit_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q, void *stream) {
   t_err[0] = 0;
   if (count < 0) return fail(VIT_EINVAL, "count = %lld must be >= 0", (long long)count);

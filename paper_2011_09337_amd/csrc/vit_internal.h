@@ -94,6 +94,11 @@ struct CopyRange {
 // Copy `count` ranges listed in device memory (vit_copy.hip).
 hipError_t launch_copy_list(const CopyRange *ranges, int32_t count, hipStream_t stream);
 
+// Launch the de-puncturer (vit_depuncture.hip): pattern bits mask[p*beta + b],
+// kept_per_period of them set.
+hipError_t launch_depuncture(const void *in, int llr_type, uint64_t mask, int32_t period, int32_t beta,
+                             int32_t kept_per_period, int64_t stages, void *out, hipStream_t stream);
+
 // Launch the int8 quantiser (vit_quantize.hip) on `stream`.
 hipError_t launch_quantize(const float *llr, int64_t count, float scale, int8_t *q, hipStream_t stream);
 

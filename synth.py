@@ -15,6 +15,8 @@ Channel model:
 The paper prints the noise deviation in a garbled form; the reading above is
 the standard one and is pinned by the raw bit-error-rate test Q(sqrt(2R Eb/N0)).
 """
+import math
+
 import numpy as np
 
 # Codes of the workloads: (k, generators in octal, listed in output order).
@@ -73,6 +75,30 @@ def make_stream(code_name, n, ebn0_db, seed, terminated=True):
     coded = encode(k, gens, bits, terminated)
     llr = awgn_llr(coded, ebn0_db, len(gens), rng)
     return bits, llr
+
+
+def puncture(values, mask):
+    """Transmitter side of puncturing: keep the values (time-major, beta per
+    stage) whose slot the (period, beta) 0/1 pattern marks."""
+    mask = np.asarray(mask, dtype=bool)
+    period, beta = mask.shape
+    v = np.asarray(values).reshape(-1, beta)
+    keep = np.tile(mask, (v.shape[0] // period + 1, 1))[: v.shape[0]]
+    return v[keep]
+
+
+def make_punctured_stream(code_name, n, ebn0_db, seed, mask, terminated=True):
+    """Bits, then the punctured coded bits sent over BPSK/AWGN at the punctured
+    rate (LLR = 2y/sigma^2, float64 rounded once to float32)."""
+    k, gens = CODES[code_name]
+    rng = np.random.default_rng(seed)
+    bits = info_bits(n, rng)
+    sent = puncture(encode(k, gens, bits, terminated), mask)
+    mask = np.asarray(mask, dtype=bool)
+    rate = mask.shape[0] / mask.sum()
+    sigma = math.sqrt(1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0)))
+    y = (1.0 - 2.0 * sent.astype(np.float64)) + sigma * rng.standard_normal(sent.size)
+    return bits, (2.0 * y / sigma ** 2).astype(np.float32)
 
 
 def hard_bits(llr):
