@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--subframe-overlap", type=int, default=None,
+                    help="headline decode with the two-subframe traceback and this inner overlap (words)")
+    ap.add_argument("--no-subframe-probe", action="store_true",
+                    help="skip the side measurement of the two-subframe traceback")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
@@ -87,16 +91,16 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def time_decode(vit, torch, code, llr_d, out_d, n, L, v, steps, warmup):
+def time_decode(vit, torch, code, llr_d, out_d, n, L, v, steps, warmup, sub=None):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream)
+        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, subframe_overlap=sub)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record(stream)
     for _ in range(steps):
-        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream)
+        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, subframe_overlap=sub)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -479,7 +483,8 @@ def main():
     sweep = {}
     for L in Ls:
         ms, wall = time_decode(vit, torch, code, llr_d, out_d, n, L, v,
-                               args.steps if L == args.L else max(3, args.steps // 4), args.warmup)
+                               args.steps if L == args.L else max(3, args.steps // 4), args.warmup,
+                               sub=args.subframe_overlap)
         g = vit.vit_query_geometry(code, n, L, v)
         ops = 4.0 * (1 << (k - 1)) * g.stages_total
         sweep[L] = {"ms": ms, "mbps": n / (ms * 1e-3) / 1e6, "tops": ops / (ms * 1e-3) / 1e12,
@@ -495,10 +500,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     # decode once more for the BER of the headline configuration
-    vit.decode(code, llr_d, n, args.L, v, out=out_d)
+    vit.decode(code, llr_d, n, args.L, v, out=out_d, subframe_overlap=args.subframe_overlap)
     torch.cuda.synchronize()
     got = synth.unpack_bits(out_d.cpu().numpy(), n)
     ber = float(np.mean(got != bits))
+    # side measurement: one trace per block vs two subframes (Sec. IV-D)
+    subframe = None
+    if not args.no_subframe_probe:
+        subframe = {}
+        for W in (None, 0, 1, 2):
+            ms_w, _ = time_decode(vit, torch, code, llr_d, out_d, n, args.L, v, max(3, args.steps // 2),
+                                  args.warmup, sub=W)
+            vit.decode(code, llr_d, n, args.L, v, out=out_d, subframe_overlap=W)
+            torch.cuda.synchronize()
+            ber_w = float(np.mean(synth.unpack_bits(out_d.cpu().numpy(), n) != bits))
+            subframe["one" if W is None else f"W{W}"] = {"mbps": round(n / (ms_w * 1e-3) / 1e6, 1),
+                                                         "ber": ber_w}
 
     llr_bytes = llr.nbytes
     hbm_alg_bytes = llr_bytes + (n + 7) // 8  # LLRs read once + packed output
@@ -545,11 +562,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"K=7 r1/2 (171/133) terminated stream of 2^{args.n_log2} info bits, FP32 LLRs, "
                                f"BPSK/AWGN Eb/N0={args.ebn0} dB; blocked L={args.L}, v={v} (v1={v // 2}, "
-                               f"v2={v - v // 2})",
-                   "n_bits": n, "L": args.L, "v": v, "ebn0_db": args.ebn0},
+                               f"v2={v - v // 2})" + ("" if args.subframe_overlap is None else
+                                                      f"; traceback in two subframes, inner overlap "
+                                                      f"{args.subframe_overlap} words"),
+                   "n_bits": n, "L": args.L, "v": v, "ebn0_db": args.ebn0,
+                   "subframe_overlap": args.subframe_overlap},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ber": ber,
+        "subframe_traceback": subframe,
         "batched": batched,
         "serving": serving,
         "sweep": {str(L): {"mbps": round(s["mbps"], 1), "ms": round(s["ms"], 4),

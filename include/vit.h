@@ -84,6 +84,18 @@ typedef struct {
   int32_t check_finite;  /* reserved, must be 0                                  */
   int32_t reserved;
   void *stream;          /* hipStream_t to launch on; NULL = default stream      */
+  /* Subframe traceback (Sec. IV-D): 1 (default) traces each block back once
+   * from its end; 2 splits the trace into two chains run side by side.  The
+   * block's survivor words (W = (k-1)*floor(32/(k-1)) stages each, counted
+   * from the block end) are split so that the lower chain starts at a word
+   * boundary, from the state with the best metric there (lowest index on
+   * ties), and its decisions are kept only subframe_overlap words below that
+   * boundary; blocks with fewer than subframe_overlap + 2 words down to the
+   * first core bit are traced once.  The output then differs from the
+   * one-trace decode where the lower chain's start state is wrong and the
+   * overlap does not correct it. */
+  int32_t subframes;
+  int32_t subframe_overlap; /* inner overlap in survivor words, >= 0 (default 2) */
 } vit_opts;
 
 /* Decode n information bits from FP32 LLRs with blocks of L core bits and
@@ -128,7 +140,8 @@ int vit_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q, voi
 int vit_depuncture(const void *received, int64_t received_count, int32_t llr_type, const uint8_t *mask,
                    int32_t period, int32_t beta, int64_t stages, void *out, void *stream);
 
-/* Default options: FP32, terminated, v1 = floor(v/2), default stream. */
+/* Default options: FP32, terminated, v1 = floor(v/2), default stream, one
+ * traceback per block. */
 vit_opts vit_opts_default(void);
 
 /* Geometry of a blocked decode, computed on the host (no device needed). */

@@ -23,11 +23,14 @@ __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Serve
            "VIT_TIE_LOWER_PRED"]
 
 
-def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=None):
+def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_overlap=None, out=None, stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
     values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
-    Returns (or fills) a uint8 device tensor of ceil(n/8) packed bytes.
-    Asynchronous on `stream` (default: torch's current stream)."""
+    subframe_overlap: None traces each block back once; an integer W >= 0
+    splits the traceback in two subframes with W survivor words of inner
+    overlap (vit_opts.subframes = 2).  Returns (or fills) a uint8 device
+    tensor of ceil(n/8) packed bytes.  Asynchronous on `stream` (default:
+    torch's current stream)."""
     import torch
 
     if not llr.is_cuda or not llr.is_contiguous():
@@ -52,6 +55,9 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, out=None, stream=Non
     opts.llr_type = llr_type
     opts.terminated = 1 if terminated else 0
     opts.v1 = -1 if v1 is None else int(v1)
+    if subframe_overlap is not None:
+        opts.subframes = 2
+        opts.subframe_overlap = int(subframe_overlap)
     if stream is None:
         stream = torch.cuda.current_stream(llr.device)
     opts.stream = stream.cuda_stream

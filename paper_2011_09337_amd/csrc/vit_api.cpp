@@ -117,6 +117,8 @@ vit_opts vit_opts_default(void) {
   o.v1 = -1;
   o.check_finite = 0;
   o.stream = nullptr;
+  o.subframes = 1;
+  o.subframe_overlap = 2;
   return o;
 }
 
@@ -158,6 +160,9 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8 && o.llr_type != VIT_LLR_HARD)
     return fail(VIT_EINVAL, "unknown llr_type %d", o.llr_type);
   if (o.check_finite != 0) return fail(VIT_EUNSUPPORTED, "check_finite is not implemented");
+  if (o.subframes != 1 && o.subframes != 2) return fail(VIT_EINVAL, "subframes = %d (1 or 2)", o.subframes);
+  if (o.subframes == 2 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
+    return fail(VIT_EINVAL, "subframe_overlap = %d outside [0, 2^24]", o.subframe_overlap);
   Geometry g;
   int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
   if (st) return st;
@@ -188,6 +193,7 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   a.terminated = o.terminated;
   a.llr_type = o.llr_type;
   a.max_block_stages = (int32_t)g.max_block_stages;
+  a.tb_overlap = o.subframes == 2 ? o.subframe_overlap : -1;
   int unsupported = 0;
   const char *why = "";
   hipError_t e = vit::launch_blocked(a, (hipStream_t)o.stream, &unsupported, &why);

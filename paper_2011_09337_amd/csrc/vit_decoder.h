@@ -215,6 +215,16 @@ __device__ __forceinline__ void acs_pair(float &oa, float &ob, float &xa, float 
 }
 
 // ---------------------------------------------------------------- decoder
+// Register rsel (uniform) of a per-lane register array, without branches.
+template <int REGS>
+__device__ __forceinline__ uint32_t select_reg(const uint32_t (&v)[REGS], uint32_t rsel) {
+  typedef uint32_t vec_t __attribute__((ext_vector_type(REGS)));
+  vec_t t;
+#pragma unroll
+  for (int i = 0; i < REGS; ++i) t[i] = v[i];
+  return t[rsel & (REGS - 1)];
+}
+
 template <int K, int BETA, bool STD, bool I8>
 struct Decoder {
   using Sh = Shape<K, BETA>;
@@ -432,6 +442,88 @@ struct Decoder {
     }
   }
 
+  // Slot index of the best state at a body end, where slot j holds state j
+  // with the sign convention of the body's last phase; lowest index on ties.
+  // Uniform across the wave.
+  __device__ __forceinline__ int best_state() const {
+    constexpr int qlast = (BODY - 1) % P;
+    float best = -INFINITY;
+    int lab = 0x7fffffff;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int slot = (reg << 6) | slot0;
+      const int label = slot & (S - 1);
+      const float sig = ((slot >> qlast) & 1) ? -o[reg] : o[reg];
+      if (reg == 0 || sig > best) {
+        best = sig;
+        lab = label;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const float ob = __shfl_xor(best, m);
+      const int ol = __shfl_xor(lab, m);
+      if (ob > best || (ob == best && ol < lab)) {
+        best = ob;
+        lab = ol;
+      }
+    }
+    return __builtin_amdgcn_readfirstlane(lab);
+  }
+
+  // Traceback (Algorithm 2) through one group (body) of survivor words for
+  // each of NCH independent chains, interleaved so that the scalar steps of
+  // one chain fill the latency of the other's.  ulam[c] is chain c's slot
+  // index (the current state).  Following the survivor at body offset pos
+  // replaces bit q = pos mod P of the slot index with the decision bit; the
+  // survivor words hold that bit XOR the slot's own bit q, so the step is
+  // ulam ^= (word bit) << q.  The words are bit-reversed and, per phase
+  // period p0..p0+P-1, shifted so that offset p0 + q sits at bit q: a step is
+  // one v_readlane and two scalar operations.  After a period the slot index
+  // holds that period's P decision bits; the group's decision word replaces
+  // its first survivor word in LDS when wr[c] (every lane writes the same
+  // word).
+  template <int NCH>
+  __device__ __forceinline__ void tb_groups(const int (&grp)[NCH], uint32_t (&ulam)[NCH],
+                                            const bool (&wr)[NCH]) const {
+    uint32_t dv[NCH][REGS];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int rr = 0; rr < REGS; ++rr) dv[c][rr] = __builtin_bitreverse32(lds[(grp[c] * REGS + rr) * 64 + lane]);
+    uint32_t acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0;
+#pragma unroll
+    for (int p0 = BODY - P; p0 >= 0; p0 -= P) {
+      uint32_t sh[NCH][REGS], src[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+        for (int rr = 0; rr < REGS; ++rr) sh[c][rr] = dv[c][rr] >> (32 - BODY + p0);
+        src[c] = sh[c][0];
+      }
+#pragma unroll
+      for (int q = P - 1; q >= 0; --q) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          if constexpr (REGS > 1) {
+            // the register holding slot ulam is given by bits >= 6 of the
+            // slot index, which change only at q >= 6: select at q >= 5 only
+            if (q >= 5) src[c] = select_reg<REGS>(sh[c], ulam[c] >> 6);
+          }
+          const uint32_t w = __builtin_amdgcn_readlane(src[c], (int)(ulam[c] & 63u));
+          ulam[c] ^= w & (1u << q);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) acc[c] |= (ulam[c] & (uint32_t)(S - 1)) << p0;
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      if (wr[c]) lds[(grp[c] * REGS) * 64] = acc[c];
+  }
+
   template <int Q>
   __device__ __forceinline__ void step_lane(int reg, float x, float y) {
     // unrolled by the caller, so `reg` is a constant after inlining
@@ -460,16 +552,6 @@ struct Decoder {
   }
 };
 
-// Register rsel (uniform) of a per-lane register array, without branches.
-template <int REGS>
-__device__ __forceinline__ uint32_t select_reg(const uint32_t (&v)[REGS], uint32_t rsel) {
-  typedef uint32_t vec_t __attribute__((ext_vector_type(REGS)));
-  vec_t t;
-#pragma unroll
-  for (int i = 0; i < REGS; ++i) t[i] = v[i];
-  return t[rsel & (REGS - 1)];
-}
-
 // The first (partial) body of a block: step G runs only from the entry offset
 // r on (uniform, scalar branches).  Later bodies run every step unguarded.
 #define VIT_G1(NN, M)                                        \
@@ -487,12 +569,14 @@ __device__ __forceinline__ uint32_t select_reg(const uint32_t (&v)[REGS], uint32
 // start (stage 0) at `llr` and whose decoded bits start (bit 0) at byte `out`;
 // emit core bits [cs, ce).  start_known: the window starts at the frame's
 // first stage (state 0); end_zero: it ends at the last stage of a terminated
-// frame (trace back from state 0).  Stages are frame-local; the caller
-// guarantees (e - s) * beta * sizeof(LLR) < 2^31 and cs a multiple of 8.
+// frame (trace back from state 0).  tb_overlap >= 0 splits the traceback in
+// two subframes (Sec. IV-D) with that many groups of inner overlap; -1 keeps
+// one.  Stages are frame-local; the caller guarantees (e - s) * beta *
+// sizeof(LLR) < 2^31 and cs a multiple of 8.
 template <int K, int BETA, bool STD, bool I8>
 __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const void *llr, uint8_t *out,
                                              int64_t s, int64_t e, int64_t cs, int64_t ce, bool start_known,
-                                             bool end_zero, const uint32_t *gen) {
+                                             bool end_zero, int tb_overlap, const uint32_t *gen) {
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
   (void)T;
@@ -507,6 +591,21 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   D.s_lo = (int)s;
   D.s_hi = (int)e - 1;
   D.body = 0;
+
+  // Traceback geometry.  Groups (bodies) grp_lo .. nbody-1 hold the stages
+  // from the one with the first core bit to the block end.  Split into two
+  // subframes (Sec. IV-D) when there are at least tb_overlap + 2 of them: the
+  // lower chain starts at the end of group gsnap from the best state there
+  // and traces down to grp_lo; the upper chain traces from the block end down
+  // to gA_lo, tb_overlap groups below gsnap + 1; the lower chain's decisions
+  // are kept only below gA_lo.
+  const int grp_lo = ((int)(cs - s) + r) / BODY;
+  int gsnap = -1, gA_lo = grp_lo;
+  if (tb_overlap >= 0 && nbody - grp_lo >= tb_overlap + 2) {
+    const int mB0 = (nbody - grp_lo - tb_overlap) / 2;
+    gsnap = nbody - 1 - mB0;
+    gA_lo = gsnap + 1 - tb_overlap;
+  }
 
   // Initial metrics: state 0 known at the stream start, else all zero.  The
   // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
@@ -534,85 +633,56 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
     D.body = 0;
     D.fetch_entry(gen, r, D.xn, D.yn);
   }
+  // At each body end slot j holds state j: the lower subframe's start state
+  // is taken there.
+  int lam_b = 0;
   D.body = 0;
   D.refresh_addresses();
   VIT_X32(VIT_G1, BODY)
+  if (gsnap == 0) lam_b = D.best_state();
   for (D.body = 1; D.body < nbody; ++D.body) {
     D.refresh_addresses();
     VIT_X32(VIT_U1, BODY)
+    if (D.body == gsnap) lam_b = D.best_state();
   }
 
-  // ---- traceback start: after M + r (a multiple of BODY) steps, slot j holds state j.
-  constexpr int qlast = (BODY - 1) % P;
-  int lam = 0;
-  if (!end_zero) {
-    float best = -INFINITY;
-    int lab = 0x7fffffff;
-#pragma unroll
-    for (int reg = 0; reg < REGS; ++reg) {
-      const int slot = (reg << 6) | D.slot0;
-      const int label = slot & (S - 1);
-      const float sig = ((slot >> qlast) & 1) ? -D.o[reg] : D.o[reg];
-      if (reg == 0 || sig > best) {
-        best = sig;
-        lab = label;
-      }
-    }
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      const float ob = __shfl_xor(best, m);
-      const int ol = __shfl_xor(lab, m);
-      if (ob > best || (ob == best && ol < lab)) {
-        best = ob;
-        lab = ol;
-      }
-    }
-    lam = __builtin_amdgcn_readfirstlane(lab);
-  }
+  // ---- traceback start: state 0 at a terminated end, else the best state.
+  const int lam = end_zero ? 0 : D.best_state();
 
-  // ---- traceback (Algorithm 2) on the scalar unit.  lam is the slot index
-  // of the current state.  Following the survivor at body offset pos replaces
-  // bit q = pos mod P of the slot index with the decision bit; the survivor
-  // words hold that bit XOR the slot's own bit q, so the step is
-  // lam ^= (word bit) << q.  Per group the words are bit-reversed and, per
-  // phase period p0..p0+P-1, shifted so that offset p0 + q sits at bit q:
-  // a step is one v_readlane and two scalar operations.  The decision bit at
-  // offset g is the input bit of offset g - (k-1) (the oldest input of the
-  // state), so the decision stream, followed by the k-1 bits of the start
-  // slot, is the decoded sequence shifted by k-1: bit t of the output is
-  // stream bit (t - stage_base) + k - 1.  Each group's stream word replaces
-  // the first survivor word of its group in LDS.
+  // ---- traceback on the scalar unit (Decoder::tb_groups).  The decision bit
+  // at offset g is the input bit of offset g - (k-1) (the oldest input of the
+  // state), so the decision stream, followed by the k-1 bits of the upper
+  // chain's start slot, is the decoded sequence shifted by k-1: bit t of the
+  // output is stream bit (t - stage_base) + k - 1.
   // The traceback is a short serial chain of scalar steps: raise the wave's
   // issue priority while it runs so that waves in their forward pass do not
   // stretch it (measured: about 8% faster overall).
   __builtin_amdgcn_s_setprio(1);
   const uint32_t lam_start = (uint32_t)lam;
-  const int grp_lo = ((int)(cs - s) + r) / BODY;
-  uint32_t ulam = (uint32_t)lam;
-  for (int grp = nbody - 1; grp >= grp_lo; --grp) {
-    uint32_t dv[REGS];
-#pragma unroll
-    for (int rr = 0; rr < REGS; ++rr) dv[rr] = __builtin_bitreverse32(D.lds[(grp * REGS + rr) * 64 + D.lane]);
-    uint32_t acc = 0;
-#pragma unroll
-    for (int p0 = BODY - P; p0 >= 0; p0 -= P) {
-      uint32_t sh[REGS];
-#pragma unroll
-      for (int rr = 0; rr < REGS; ++rr) sh[rr] = dv[rr] >> (32 - BODY + p0);
-      uint32_t src = sh[0];
-#pragma unroll
-      for (int q = P - 1; q >= 0; --q) {
-        if constexpr (REGS > 1) {
-          // the register holding slot ulam is given by bits >= 6 of the slot
-          // index, which change only at q >= 6: select at q >= 5 only
-          if (q >= 5) src = select_reg<REGS>(sh, ulam >> 6);
-        }
-        const uint32_t w = __builtin_amdgcn_readlane(src, (int)(ulam & 63u));
-        ulam ^= w & (1u << q);
-      }
-      acc |= (ulam & (uint32_t)(S - 1)) << p0;
+  if (gsnap < 0) {
+    uint32_t u1[1] = {(uint32_t)lam};
+    const bool w1[1] = {true};
+    for (int grp = nbody - 1; grp >= grp_lo; --grp) {
+      const int g1[1] = {grp};
+      D.template tb_groups<1>(g1, u1, w1);
     }
-    D.lds[(grp * REGS) * 64] = acc;  // every lane writes the same word
+  } else {
+    // chains A (upper, from the block end) and B (lower, from gsnap) step
+    // together; B is at most one group longer and reads each overlap group
+    // before A rewrites it
+    uint32_t u2[2] = {(uint32_t)lam, (uint32_t)lam_b};
+    const int len_a = nbody - gA_lo, len_b = gsnap - grp_lo + 1;
+    for (int i = 0; i < len_a; ++i) {
+      const int g2[2] = {nbody - 1 - i, gsnap - i};
+      const bool w2[2] = {true, gsnap - i < gA_lo};
+      D.template tb_groups<2>(g2, u2, w2);
+    }
+    if (len_b > len_a) {
+      uint32_t u1[1] = {u2[1]};
+      const int g1[1] = {gsnap - len_a};
+      const bool w1[1] = {true};
+      D.template tb_groups<1>(g1, u1, w1);
+    }
   }
 
   __builtin_amdgcn_s_setprio(0);
@@ -637,8 +707,12 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   }
 }
 
+// For 5 <= k <= 7 the register budget is held to 64 VGPRs (eight waves per
+// SIMD): left to itself the scheduler trades occupancy for deeper prefetch of
+// branch metrics in some instances; the few scalar spills this costs are in
+// the block prologue.
 template <int K, int BETA, bool STD, bool I8>
-__global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 5 && K <= 7 ? 8 : 1, 8))) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, I8>;
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
@@ -677,7 +751,7 @@ __global__ __launch_bounds__(256) void vit_blocked_kernel(DecodeArgs a, int lds_
     const int64_t ce = (cs + a.L < a.n) ? cs + a.L : a.n;
     const int64_t s = (cs - a.v1 > 0) ? cs - a.v1 : 0;
     const int64_t e = (ce + a.v2 < a.N) ? ce + a.v2 : a.N;
-    decode_block(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.gen);
+    decode_block(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.tb_overlap, a.gen);
   }
 }
 
@@ -707,7 +781,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
     const WorkItem it = items[idx];
     const char *base = (const char *)a.llr + it.llr_off;
     decode_block(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,
-                 (it.flags & 2) != 0, a.gen);
+                 (it.flags & 2) != 0, -1, a.gen);
   }
 }
 

@@ -39,8 +39,8 @@ def test_abi_version(vit):
 
 def test_opts_default(vit):
     o = vit.vit_opts_default()
-    assert o.size == 32 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
-    assert o.stream is None
+    assert o.size == 40 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
+    assert o.stream is None and o.subframes == 1 and o.subframe_overlap == 2
 
 
 K7 = (7, (0o171, 0o133))
@@ -91,6 +91,10 @@ def test_invalid_arguments(vit):
     o = vit.vit_opts_default()
     o.terminated = 2
     _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+    for sub, ov in ((0, 2), (3, 2), (2, -1), (2, (1 << 24) + 1)):
+        o = vit.vit_opts_default()
+        o.subframes, o.subframe_overlap = sub, ov
+        _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
 
 
 def test_unsupported_arguments(vit):
