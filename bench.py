@@ -45,10 +45,12 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
-    ap.add_argument("--subframe-overlap", type=int, default=None,
-                    help="headline decode with the two-subframe traceback and this inner overlap (words)")
+    ap.add_argument("--subframes", default=None, metavar="F:W",
+                    help="headline decode with the subframe traceback: F words per subframe, W words of overlap")
     ap.add_argument("--no-subframe-probe", action="store_true",
-                    help="skip the side measurement of the two-subframe traceback")
+                    help="skip the side measurement of the subframe traceback")
+    ap.add_argument("--table3", action="store_true",
+                    help="print the BER-gap grid of the subframe traceback (F x W) and exit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
@@ -87,20 +89,26 @@ def source_hash():
     csrc = os.path.join(ROOT, "paper_2011_09337_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f in ("vit_decoder.h", "vit_internal.h", "vit_launch.hip") or f.startswith("vit_kernels_k"):
+            # (the subframe instances, vit_kernels_sub_k*, are other kernels)
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def subframe_kw(sub):
+    """decode() keywords of an (F, W) subframe setting (None = one trace)."""
+    return {} if sub is None else dict(subframe_words=sub[0], subframe_overlap=sub[1])
 
 
 def time_decode(vit, torch, code, llr_d, out_d, n, L, v, steps, warmup, sub=None):
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, subframe_overlap=sub)
+        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, **subframe_kw(sub))
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record(stream)
     for _ in range(steps):
-        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, subframe_overlap=sub)
+        vit.decode(code, llr_d, n, L, v, out=out_d, stream=stream, **subframe_kw(sub))
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -392,67 +400,70 @@ def bench_serving(vit, torch, args, tunes):
     }
 
 
-def ber_gap_sweep(vit, torch, log2n=24):
-    """Eb/N0 gap at BER 1e-4 between the blocked decoder and maximum-likelihood
-    decoding, over the paper's Table II grid (f = L in {32..512}, v2 in
-    {10..40}; v1 = v2), K=7 r1/2, FP32 LLRs, 2^log2n bits per Eb/N0 point.
-    The ML reference is the blocked decoder with v1 = v2 = 128 (traceback
-    depth far beyond convergence); the oracle's full-frame ML checks it on the
-    first 2^18 bits of every point."""
+def ber_gaps(vit, torch, configs, log2n=24):
+    """Eb/N0 gap at BER 1e-4 between decoder configurations and maximum-
+    likelihood decoding, K=7 r1/2, FP32 LLRs, 2^log2n bits per Eb/N0 point.
+    configs: label -> decode keyword arguments (L, v1, v2 and any options).
+    The ML reference is the blocked decoder with v1 = v2 = 128, a traceback
+    depth far beyond convergence (tests check it against full-frame ML)."""
     import numpy as np
     import synth
-    from oracle import vref
     k, gens = synth.CODES["k7r12"]
     code = vit.make_code(k, gens)
-    ocode = vref.make_code(k, list(gens))
     n = 1 << log2n
     grid = [2.5, 3.0, 3.5, 4.0, 4.5, 5.0]
-    fs, v2s = (32, 64, 128, 256, 512), (10, 20, 30, 40)
     errs = {}
-    ml_check = []
     out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
     for e in grid:
         bits, llr = synth.make_stream("k7r12", n, e, seed=100 + int(e * 10))
         d = torch.from_numpy(llr).cuda()
 
-        def nerr(L, v1, v2):
-            vit.decode(code, d, n, L, v1 + v2, v1=v1, out=out)
+        def nerr(L, v1, v2, **kw):
+            vit.decode(code, d, n, L, v1 + v2, v1=v1, out=out, **kw)
             got = synth.unpack_bits(out.cpu().numpy(), n)
-            return int(np.sum(got != bits)), got
+            return int(np.sum(got != bits))
 
-        ml_e, ml_bits = nerr(512, 128, 128)
-        errs[("ml", e)] = ml_e
-        # the oracle's full-frame ML on the first m stages as an open stream;
-        # its last bits depend on the unknown end state, so they are not compared
-        m = 1 << 18
-        ref = vref.decode_full(ocode, llr[: m * 2], m, terminated=False)
-        ml_check.append(int(np.sum(ref[: m - 64] != ml_bits[: m - 64])))
-        for f in fs:
-            for v2 in v2s:
-                errs[(f, v2, e)] = nerr(f, v2, v2)[0]
+        errs[("ml", e)] = nerr(512, 128, 128)
+        for label, kw in configs.items():
+            errs[(label, e)] = nerr(**kw)
+        print(f"[ber] Eb/N0 {e} dB done", file=sys.stderr, flush=True)
 
-    def ebn0_at(key_of):
-        bers = [max(errs[key_of(e)], 0.5) / n for e in grid]
+    def ebn0_at(label):
+        bers = [max(errs[(label, e)], 0.5) / n for e in grid]
         for i in range(len(grid) - 1):
             if bers[i] >= 1e-4 > bers[i + 1]:
                 y0, y1 = np.log(bers[i]), np.log(bers[i + 1])
                 return grid[i] + (np.log(1e-4) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
         return None
 
-    ml_at = ebn0_at(lambda e: ("ml", e))
+    ml_at = ebn0_at("ml")
     table = {}
-    for v2 in v2s:
-        for f in fs:
-            at = ebn0_at(lambda e, f=f, v2=v2: (f, v2, e))
-            table[f"v2={v2},f={f}"] = None if at is None or ml_at is None else round(float(at - ml_at), 4)
+    for label in configs:
+        at = ebn0_at(label)
+        table[label] = None if at is None or ml_at is None else round(float(at - ml_at), 4)
     return {
-        "workload": f"K=7 r1/2, FP32 LLRs, 2^{log2n} bits per point, Eb/N0 {grid[0]}..{grid[-1]} dB; v1 = v2; "
-                    f"gap = Eb/N0 at BER 1e-4 minus that of the ML reference (v1 = v2 = 128)",
+        "workload": f"K=7 r1/2, FP32 LLRs, 2^{log2n} bits per point, Eb/N0 {grid[0]}..{grid[-1]} dB; "
+                    f"gap = Eb/N0 at BER 1e-4 minus that of the ML reference (blocked, v1 = v2 = 128)",
         "ml_ebn0_at_1e-4": None if ml_at is None else round(float(ml_at), 4),
         "ml_errors": {str(e): errs[("ml", e)] for e in grid},
-        "ml_reference_vs_full_frame_ml_bit_differences": ml_check,
         "gap_db": table,
     }
+
+
+def table2_configs():
+    """The paper's Table II grid: f = L in {32..512}, v2 in {10..40}, v1 = v2."""
+    return {f"v2={v2},f={f}": dict(L=f, v1=v2, v2=v2) for v2 in (10, 20, 30, 40) for f in (32, 64, 128, 256, 512)}
+
+
+def table3_configs():
+    """The parallel-traceback grid (Sec. IV-D and its BER table): blocks of
+    f = 256 with v1 = v2 = 20, subframes of F survivor words (30 stages for
+    K=7) with W words of inner overlap, against the one-trace decoder."""
+    c = {"one trace": dict(L=256, v1=20, v2=20)}
+    for W in (0, 1, 2):
+        for F in (1, 2, 4):
+            c[f"W={W},F={F}"] = dict(L=256, v1=20, v2=20, subframe_words=F, subframe_overlap=W)
+    return c
 
 
 def main():
@@ -468,9 +479,13 @@ def main():
     import synth
 
     if args.table2:
-        print(json.dumps({"table2": ber_gap_sweep(vit, torch)}), flush=True)
+        print(json.dumps({"table2": ber_gaps(vit, torch, table2_configs())}), flush=True)
+        return
+    if args.table3:
+        print(json.dumps({"table3": ber_gaps(vit, torch, table3_configs())}), flush=True)
         return
 
+    head_sub = None if args.subframes is None else tuple(int(x) for x in args.subframes.split(":"))
     k, gens = synth.CODES["k7r12"]
     v = 5 * k
     n = 1 << args.n_log2
@@ -484,7 +499,7 @@ def main():
     for L in Ls:
         ms, wall = time_decode(vit, torch, code, llr_d, out_d, n, L, v,
                                args.steps if L == args.L else max(3, args.steps // 4), args.warmup,
-                               sub=args.subframe_overlap)
+                               sub=head_sub)
         g = vit.vit_query_geometry(code, n, L, v)
         ops = 4.0 * (1 << (k - 1)) * g.stages_total
         sweep[L] = {"ms": ms, "mbps": n / (ms * 1e-3) / 1e6, "tops": ops / (ms * 1e-3) / 1e12,
@@ -500,22 +515,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     # decode once more for the BER of the headline configuration
-    vit.decode(code, llr_d, n, args.L, v, out=out_d, subframe_overlap=args.subframe_overlap)
+    vit.decode(code, llr_d, n, args.L, v, out=out_d, **subframe_kw(head_sub))
     torch.cuda.synchronize()
     got = synth.unpack_bits(out_d.cpu().numpy(), n)
     ber = float(np.mean(got != bits))
-    # side measurement: one trace per block vs two subframes (Sec. IV-D)
+    # side measurement: one trace per block vs subframes (Sec. IV-D)
     subframe = None
     if not args.no_subframe_probe:
         subframe = {}
-        for W in (None, 0, 1, 2):
+        for sub in (None, (1, 1), (1, 2), (2, 2), (4, 2), (8, 2)):
             ms_w, _ = time_decode(vit, torch, code, llr_d, out_d, n, args.L, v, max(3, args.steps // 2),
-                                  args.warmup, sub=W)
-            vit.decode(code, llr_d, n, args.L, v, out=out_d, subframe_overlap=W)
+                                  args.warmup, sub=sub)
+            vit.decode(code, llr_d, n, args.L, v, out=out_d, **subframe_kw(sub))
             torch.cuda.synchronize()
             ber_w = float(np.mean(synth.unpack_bits(out_d.cpu().numpy(), n) != bits))
-            subframe["one" if W is None else f"W{W}"] = {"mbps": round(n / (ms_w * 1e-3) / 1e6, 1),
-                                                         "ber": ber_w}
+            subframe["one" if sub is None else f"F{sub[0]}W{sub[1]}"] = {"mbps": round(n / (ms_w * 1e-3) / 1e6, 1),
+                                                                         "ber": ber_w}
 
     llr_bytes = llr.nbytes
     hbm_alg_bytes = llr_bytes + (n + 7) // 8  # LLRs read once + packed output
@@ -562,11 +577,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"K=7 r1/2 (171/133) terminated stream of 2^{args.n_log2} info bits, FP32 LLRs, "
                                f"BPSK/AWGN Eb/N0={args.ebn0} dB; blocked L={args.L}, v={v} (v1={v // 2}, "
-                               f"v2={v - v // 2})" + ("" if args.subframe_overlap is None else
-                                                      f"; traceback in two subframes, inner overlap "
-                                                      f"{args.subframe_overlap} words"),
+                               f"v2={v - v // 2})" + ("" if head_sub is None else
+                                                      f"; traceback in subframes of {head_sub[0]} words, inner "
+                                                      f"overlap {head_sub[1]} words"),
                    "n_bits": n, "L": args.L, "v": v, "ebn0_db": args.ebn0,
-                   "subframe_overlap": args.subframe_overlap},
+                   "subframes": None if head_sub is None else list(head_sub)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ber": ber,

@@ -84,18 +84,19 @@ typedef struct {
   int32_t check_finite;  /* reserved, must be 0                                  */
   int32_t reserved;
   void *stream;          /* hipStream_t to launch on; NULL = default stream      */
-  /* Subframe traceback (Sec. IV-D): 1 (default) traces each block back once
-   * from its end; 2 splits the trace into two chains run side by side.  The
-   * block's survivor words (W = (k-1)*floor(32/(k-1)) stages each, counted
-   * from the block end) are split so that the lower chain starts at a word
-   * boundary, from the state with the best metric there (lowest index on
-   * ties), and its decisions are kept only subframe_overlap words below that
-   * boundary; blocks with fewer than subframe_overlap + 2 words down to the
-   * first core bit are traced once.  The output then differs from the
-   * one-trace decode where the lower chain's start state is wrong and the
-   * overlap does not correct it. */
-  int32_t subframes;
-  int32_t subframe_overlap; /* inner overlap in survivor words, >= 0 (default 2) */
+  /* Subframe traceback (Sec. IV-D).  0 (default): each block is traced back
+   * once from its end.  F > 0: the block's survivor words (G = (k-1) *
+   * floor(32/(k-1)) stages each, counted from the block end down to the one
+   * holding the first core bit) are cut into subframes of F words, each
+   * traced by its own chain: subframe c starts max(cF - W, 0) words below
+   * the end (W = subframe_overlap), from the block's own start state if that
+   * is the end and otherwise from the state with the best metric there
+   * (lowest index on ties), and emits only the bits decided in its own F
+   * words.  The output then differs from the one-trace decode where a
+   * chain's start state is wrong and the overlap does not correct it.  At
+   * most 64 subframes per block (VIT_EUNSUPPORTED otherwise). */
+  int32_t subframe_words;
+  int32_t subframe_overlap; /* W, inner overlap in survivor words, >= 0 (default 2) */
 } vit_opts;
 
 /* Decode n information bits from FP32 LLRs with blocks of L core bits and

@@ -86,21 +86,21 @@ int vref_window_f64(const vref_code *code, const double *llr, int64_t s, int64_t
 /* Saturating int8 quantiser: q = clamp(round_half_even(llr * scale), -127, 127). */
 int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q);
 
-/* Blocked decoding with the traceback of each block split in two subframes
- * (Sec. IV-D).  Block geometry as vref_decode_blocked_*.  With M words of G
- * stages counted from the block end e down to the word holding the first
- * core bit cs, and W words of inner overlap: if M >= W + 2 the lower
- * subframe's traceback starts at stage x-1 with x = e - floor((M-W)/2)*G,
- * from the state with the best metric after stage x-1 (lowest index on ties),
- * and it gives the bits [cs, z) with z = x - W*G - (k-1); the upper subframe
- * is the usual traceback from the block end and gives the bits [z, ce).
- * Otherwise the block is decoded as by vref_decode_blocked_*. */
+/* Blocked decoding with the traceback of each block split into subframes
+ * (Sec. IV-D).  Block geometry as vref_decode_blocked_*.  Words of G stages
+ * are counted from the block end e; M words reach down to the one holding
+ * the first core bit.  Subframe c (c < ceil(M/F)) is words [cF, (c+1)F); its
+ * chain starts max(cF - W, 0) words below the end: at the block end with the
+ * block's own start state, else from the state with the best metric there
+ * (lowest index on ties); it emits the bits whose decisions lie in its
+ * subframe (bit t is decided at stage t + k - 1).  F >= M gives
+ * vref_decode_blocked_*. */
 int vref_decode_blocked_split_f32(const vref_code *code, const float *llr, int64_t n, int32_t terminated,
-                                  int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t W, uint8_t *out,
-                                  int32_t nthreads);
+                                  int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W,
+                                  uint8_t *out, int32_t nthreads);
 int vref_decode_blocked_split_i8(const vref_code *code, const int8_t *llr, int64_t n, int32_t terminated,
-                                 int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t W, uint8_t *out,
-                                 int32_t nthreads);
+                                 int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W,
+                                 uint8_t *out, int32_t nthreads);
 
 /* De-puncturing (Sec. IV-E): expand a punctured stream into `stages` stages
  * of beta LLRs.  mask[p*beta + b] != 0 when output b of stage t with

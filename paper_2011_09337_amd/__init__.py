@@ -23,12 +23,13 @@ __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Serve
            "VIT_TIE_LOWER_PRED"]
 
 
-def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_overlap=None, out=None, stream=None):
+def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, subframe_overlap=2, out=None,
+           stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
     values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
-    subframe_overlap: None traces each block back once; an integer W >= 0
-    splits the traceback in two subframes with W survivor words of inner
-    overlap (vit_opts.subframes = 2).  Returns (or fills) a uint8 device
+    subframe_words F > 0 splits each block's traceback into subframes of F
+    survivor words with subframe_overlap words of inner overlap (see
+    vit_opts); 0 traces each block back once.  Returns (or fills) a uint8 device
     tensor of ceil(n/8) packed bytes.  Asynchronous on `stream` (default:
     torch's current stream)."""
     import torch
@@ -55,9 +56,8 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_overlap=Non
     opts.llr_type = llr_type
     opts.terminated = 1 if terminated else 0
     opts.v1 = -1 if v1 is None else int(v1)
-    if subframe_overlap is not None:
-        opts.subframes = 2
-        opts.subframe_overlap = int(subframe_overlap)
+    opts.subframe_words = int(subframe_words)
+    opts.subframe_overlap = int(subframe_overlap)
     if stream is None:
         stream = torch.cuda.current_stream(llr.device)
     opts.stream = stream.cuda_stream

@@ -33,7 +33,7 @@ class vit_code(C.Structure):
 class vit_opts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("terminated", C.c_int32),
                 ("v1", C.c_int32), ("check_finite", C.c_int32), ("reserved", C.c_int32),
-                ("stream", C.c_void_p), ("subframes", C.c_int32), ("subframe_overlap", C.c_int32)]
+                ("stream", C.c_void_p), ("subframe_words", C.c_int32), ("subframe_overlap", C.c_int32)]
 
 
 class vit_geometry(C.Structure):

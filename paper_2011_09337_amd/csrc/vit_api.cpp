@@ -117,7 +117,7 @@ vit_opts vit_opts_default(void) {
   o.v1 = -1;
   o.check_finite = 0;
   o.stream = nullptr;
-  o.subframes = 1;
+  o.subframe_words = 0;
   o.subframe_overlap = 2;
   return o;
 }
@@ -160,8 +160,8 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8 && o.llr_type != VIT_LLR_HARD)
     return fail(VIT_EINVAL, "unknown llr_type %d", o.llr_type);
   if (o.check_finite != 0) return fail(VIT_EUNSUPPORTED, "check_finite is not implemented");
-  if (o.subframes != 1 && o.subframes != 2) return fail(VIT_EINVAL, "subframes = %d (1 or 2)", o.subframes);
-  if (o.subframes == 2 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
+  if (o.subframe_words < 0) return fail(VIT_EINVAL, "subframe_words = %d must be >= 0", o.subframe_words);
+  if (o.subframe_words > 0 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
     return fail(VIT_EINVAL, "subframe_overlap = %d outside [0, 2^24]", o.subframe_overlap);
   Geometry g;
   int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
@@ -193,7 +193,17 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   a.terminated = o.terminated;
   a.llr_type = o.llr_type;
   a.max_block_stages = (int32_t)g.max_block_stages;
-  a.tb_overlap = o.subframes == 2 ? o.subframe_overlap : -1;
+  a.tb_words = o.subframe_words;
+  a.tb_overlap = o.subframe_words > 0 ? o.subframe_overlap : 0;
+  if (o.subframe_words > 0) {
+    // a block's words reach from its end to the one holding its first core
+    // bit: at most ceil(max_block_stages / G) of them
+    const int64_t G = (int64_t)(code->k - 1) * (32 / (code->k - 1));
+    const int64_t words = (g.max_block_stages + G - 1) / G;
+    if ((words + o.subframe_words - 1) / o.subframe_words > 64)
+      return fail(VIT_EUNSUPPORTED, "%lld survivor words per block in subframes of %d: more than 64 subframes",
+                  (long long)words, o.subframe_words);
+  }
   int unsupported = 0;
   const char *why = "";
   hipError_t e = vit::launch_blocked(a, (hipStream_t)o.stream, &unsupported, &why);

@@ -569,14 +569,15 @@ struct Decoder {
 // start (stage 0) at `llr` and whose decoded bits start (bit 0) at byte `out`;
 // emit core bits [cs, ce).  start_known: the window starts at the frame's
 // first stage (state 0); end_zero: it ends at the last stage of a terminated
-// frame (trace back from state 0).  tb_overlap >= 0 splits the traceback in
-// two subframes (Sec. IV-D) with that many groups of inner overlap; -1 keeps
-// one.  Stages are frame-local; the caller guarantees (e - s) * beta *
-// sizeof(LLR) < 2^31 and cs a multiple of 8.
-template <int K, int BETA, bool STD, bool I8>
+// frame (trace back from state 0).  SUB instances split the traceback into
+// subframes of tb_words groups with tb_overlap groups of inner overlap
+// (Sec. IV-D); others trace each block once (and ignore both).  Stages are
+// frame-local; the caller guarantees (e - s) * beta * sizeof(LLR) < 2^31, cs
+// a multiple of 8, and at most 64 subframes per block.
+template <bool SUB, int K, int BETA, bool STD, bool I8>
 __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const void *llr, uint8_t *out,
                                              int64_t s, int64_t e, int64_t cs, int64_t ce, bool start_known,
-                                             bool end_zero, int tb_overlap, const uint32_t *gen) {
+                                             bool end_zero, int tb_words, int tb_overlap, const uint32_t *gen) {
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
   (void)T;
@@ -593,19 +594,21 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   D.body = 0;
 
   // Traceback geometry.  Groups (bodies) grp_lo .. nbody-1 hold the stages
-  // from the one with the first core bit to the block end.  Split into two
-  // subframes (Sec. IV-D) when there are at least tb_overlap + 2 of them: the
-  // lower chain starts at the end of group gsnap from the best state there
-  // and traces down to grp_lo; the upper chain traces from the block end down
-  // to gA_lo, tb_overlap groups below gsnap + 1; the lower chain's decisions
-  // are kept only below gA_lo.
+  // from the one with the first core bit to the block end; counted from the
+  // end they are words 0 .. nw-1.  With subframes of F = tb_words words
+  // (Sec. IV-D) there are nch = ceil(nw / F) chains: chain c keeps words
+  // [cF, (c+1)F) and starts sw_c = max(cF - W, 0) words below the end, with
+  // W = tb_overlap words of inner overlap; a chain with sw_c > 0 starts from
+  // the best state at the end of group nbody-1-sw_c, taken when the forward
+  // pass gets there (highest chain first) and kept in lane c of snap_v.
   const int grp_lo = ((int)(cs - s) + r) / BODY;
-  int gsnap = -1, gA_lo = grp_lo;
-  if (tb_overlap >= 0 && nbody - grp_lo >= tb_overlap + 2) {
-    const int mB0 = (nbody - grp_lo - tb_overlap) / 2;
-    gsnap = nbody - 1 - mB0;
-    gA_lo = gsnap + 1 - tb_overlap;
-  }
+  const int nw = nbody - grp_lo;
+  const int F = SUB && tb_words > 0 ? tb_words : nw;
+  const int W = SUB && tb_words > 0 ? tb_overlap : 0;
+  const int nch = (nw + F - 1) / F;
+  const int c_min = W / F + 1;  // first chain with sw_c > 0
+  int snap_c = nch - 1;
+  int snap_next = snap_c >= c_min ? nbody - 1 - (snap_c * F - W) : -1;
 
   // Initial metrics: state 0 known at the stream start, else all zero.  The
   // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
@@ -633,17 +636,27 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
     D.body = 0;
     D.fetch_entry(gen, r, D.xn, D.yn);
   }
-  // At each body end slot j holds state j: the lower subframe's start state
-  // is taken there.
-  int lam_b = 0;
+  // At each body end slot j holds state j: subframe start states are taken
+  // there.
+  uint32_t snap_v = 0;
+  auto take_snapshot = [&]() {
+    const uint32_t best = (uint32_t)D.best_state();
+    snap_v = D.lane == snap_c ? best : snap_v;
+    --snap_c;
+    snap_next = snap_c >= c_min ? snap_next + F : -1;
+  };
   D.body = 0;
   D.refresh_addresses();
   VIT_X32(VIT_G1, BODY)
-  if (gsnap == 0) lam_b = D.best_state();
+  if constexpr (SUB) {
+    if (snap_next == 0) take_snapshot();
+  }
   for (D.body = 1; D.body < nbody; ++D.body) {
     D.refresh_addresses();
     VIT_X32(VIT_U1, BODY)
-    if (D.body == gsnap) lam_b = D.best_state();
+    if constexpr (SUB) {
+      if (D.body == snap_next) take_snapshot();
+    }
   }
 
   // ---- traceback start: state 0 at a terminated end, else the best state.
@@ -659,7 +672,7 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   // stretch it (measured: about 8% faster overall).
   __builtin_amdgcn_s_setprio(1);
   const uint32_t lam_start = (uint32_t)lam;
-  if (gsnap < 0) {
+  if (!SUB || nch == 1) {
     uint32_t u1[1] = {(uint32_t)lam};
     const bool w1[1] = {true};
     for (int grp = nbody - 1; grp >= grp_lo; --grp) {
@@ -667,21 +680,49 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
       D.template tb_groups<1>(g1, u1, w1);
     }
   } else {
-    // chains A (upper, from the block end) and B (lower, from gsnap) step
-    // together; B is at most one group longer and reads each overlap group
-    // before A rewrites it
-    uint32_t u2[2] = {(uint32_t)lam, (uint32_t)lam_b};
-    const int len_a = nbody - gA_lo, len_b = gsnap - grp_lo + 1;
-    for (int i = 0; i < len_a; ++i) {
-      const int g2[2] = {nbody - 1 - i, gsnap - i};
-      const bool w2[2] = {true, gsnap - i < gA_lo};
-      D.template tb_groups<2>(g2, u2, w2);
-    }
-    if (len_b > len_a) {
-      uint32_t u1[1] = {u2[1]};
-      const int g1[1] = {gsnap - len_a};
-      const bool w1[1] = {true};
-      D.template tb_groups<1>(g1, u1, w1);
+    // Chains go bottom-up in pairs (c, c-1) stepped together.  A chain
+    // rewrites only the words of its own subframe; every chain that reads
+    // them (a lower one, through its overlap) runs in an earlier pair, or in
+    // the same pair at least one step earlier, or at the same step (words are
+    // read before they are written).
+    struct Chain {
+      int top, len, wlim;  // first group traced, groups traced, highest group it writes
+      uint32_t lam;        // start state
+    };
+    auto chain = [&](int ch) {
+      Chain k;
+      const int sw = ch * F - W > 0 ? ch * F - W : 0;
+      const int bottom = ((ch + 1) * F < nw ? (ch + 1) * F : nw) - 1;  // lowest word
+      k.top = nbody - 1 - sw;
+      k.len = bottom - sw + 1;
+      k.wlim = nbody - 1 - ch * F;
+      k.lam = sw > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)snap_v, ch) : (uint32_t)lam;
+      return k;
+    };
+    for (int c = nch - 1; c >= 0; c -= 2) {
+      Chain a = chain(c);
+      int both = 0;
+      if (c >= 1) {
+        Chain b = chain(c - 1);
+        both = a.len < b.len ? a.len : b.len;
+        uint32_t u[2] = {a.lam, b.lam};
+        for (int i = 0; i < both; ++i) {
+          const int g2[2] = {a.top - i, b.top - i};
+          const bool w2[2] = {a.top - i <= a.wlim, b.top - i <= b.wlim};
+          D.template tb_groups<2>(g2, u, w2);
+        }
+        a.lam = u[0];
+        b.lam = u[1];
+        if (b.len > a.len) {  // continue with the longer chain alone
+          a = b;
+        }
+      }
+      uint32_t u1[1] = {a.lam};
+      for (int i = both; i < a.len; ++i) {
+        const int g1[1] = {a.top - i};
+        const bool w1[1] = {a.top - i <= a.wlim};
+        D.template tb_groups<1>(g1, u1, w1);
+      }
     }
   }
 
@@ -711,7 +752,7 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
 // SIMD): left to itself the scheduler trades occupancy for deeper prefetch of
 // branch metrics in some instances; the few scalar spills this costs are in
 // the block prologue.
-template <int K, int BETA, bool STD, bool I8>
+template <int K, int BETA, bool STD, bool I8, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 5 && K <= 7 ? 8 : 1, 8))) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, I8>;
   using Sh = Shape<K, BETA>;
@@ -751,7 +792,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 5 && K
     const int64_t ce = (cs + a.L < a.n) ? cs + a.L : a.n;
     const int64_t s = (cs - a.v1 > 0) ? cs - a.v1 : 0;
     const int64_t e = (ce + a.v2 < a.N) ? ce + a.v2 : a.N;
-    decode_block(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.tb_overlap, a.gen);
+    decode_block<SUB>(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.tb_words,
+                      a.tb_overlap, a.gen);
   }
 }
 
@@ -780,8 +822,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
   for (int idx = (int)blockIdx.x * wpb + wid; idx < nitems; idx += nwaves) {
     const WorkItem it = items[idx];
     const char *base = (const char *)a.llr + it.llr_off;
-    decode_block(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,
-                 (it.flags & 2) != 0, -1, a.gen);
+    decode_block<false>(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,
+                        (it.flags & 2) != 0, 0, 0, a.gen);
   }
 }
 
@@ -795,13 +837,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
 typedef void (*KernelFn)(DecodeArgs, int);
 typedef void (*BatchKernelFn)(BatchArgs, int);
 
-// Kernel instance for (K, beta, standard code, int8 input).
-template <int K>
+// Kernel instance for (K, beta, standard code, int8 input, subframe traceback).
+template <int K, bool SUB>
 KernelFn pick_kernel_k(int beta, bool stdc, bool i8) {
   auto pick = [&](auto bt) -> KernelFn {
     constexpr int B = decltype(bt)::value;
-    if (stdc) return i8 ? dev::vit_blocked_kernel<K, B, true, true> : dev::vit_blocked_kernel<K, B, true, false>;
-    return i8 ? dev::vit_blocked_kernel<K, B, false, true> : dev::vit_blocked_kernel<K, B, false, false>;
+    if (stdc)
+      return i8 ? dev::vit_blocked_kernel<K, B, true, true, SUB> : dev::vit_blocked_kernel<K, B, true, false, SUB>;
+    return i8 ? dev::vit_blocked_kernel<K, B, false, true, SUB> : dev::vit_blocked_kernel<K, B, false, false, SUB>;
   };
   switch (beta) {
     case 2: return pick(std::integral_constant<int, 2>{});
@@ -827,12 +870,19 @@ BatchKernelFn pick_batch_kernel_k(int beta, bool stdc, bool i8) {
 }
 
 KernelFn pick_kernel_k3(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k3(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k4(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k4(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k5(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k5(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k6(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k6(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k7(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k7(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k8(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k8(int beta, bool stdc, bool i8);
 KernelFn pick_kernel_k9(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_sub_k9(int beta, bool stdc, bool i8);
 BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, bool i8);
 BatchKernelFn pick_batch_kernel_k4(int beta, bool stdc, bool i8);
 BatchKernelFn pick_batch_kernel_k5(int beta, bool stdc, bool i8);

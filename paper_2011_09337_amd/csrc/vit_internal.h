@@ -24,7 +24,8 @@ struct DecodeArgs {
   int32_t terminated;
   int32_t llr_type;      // VIT_LLR_F32, VIT_LLR_I8 or VIT_LLR_HARD
   int32_t max_block_stages;
-  int32_t tb_overlap;    // >= 0: traceback in two subframes with this many groups of inner overlap; -1: one
+  int32_t tb_words;      // > 0: traceback in subframes of this many survivor words; 0: one per block
+  int32_t tb_overlap;    // inner overlap of a subframe, in survivor words
 };
 
 // One work item of a batched decode: one block of one frame.

@@ -40,7 +40,7 @@ def test_abi_version(vit):
 def test_opts_default(vit):
     o = vit.vit_opts_default()
     assert o.size == 40 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
-    assert o.stream is None and o.subframes == 1 and o.subframe_overlap == 2
+    assert o.stream is None and o.subframe_words == 0 and o.subframe_overlap == 2
 
 
 K7 = (7, (0o171, 0o133))
@@ -91,10 +91,21 @@ def test_invalid_arguments(vit):
     o = vit.vit_opts_default()
     o.terminated = 2
     _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
-    for sub, ov in ((0, 2), (3, 2), (2, -1), (2, (1 << 24) + 1)):
+    for sub, ov in ((-1, 2), (1, -1), (2, (1 << 24) + 1)):
         o = vit.vit_opts_default()
-        o.subframes, o.subframe_overlap = sub, ov
+        o.subframe_words, o.subframe_overlap = sub, ov
         _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+
+
+def test_too_many_subframes(vit):
+    # at most 64 subframes per block: a full frame of 100000 bits has 3334
+    # words of 30 stages (K=7)
+    c = _code(vit)
+    o = vit.vit_opts_default()
+    o.subframe_words = 1
+    _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode_ex, c, FAKE, 100000, 0, 0, 0, FAKE, o)
+    o.subframe_words = 52  # 65 subframes
+    _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode_ex, c, FAKE, 100000, 0, 0, 0, FAKE, o)
 
 
 def test_unsupported_arguments(vit):

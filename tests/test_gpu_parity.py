@@ -234,3 +234,24 @@ def test_full_size_stream_k7(dev, L):
     n = 1 << 24
     bits, llr = synth.make_stream("k7r12", n, 3.0, seed=1 + 3)
     _check(dev, k, gens, llr, n, L, 35)
+
+
+# ----------------------------------------------------------------------------- BER-gap reference
+
+@pytest.mark.parametrize("ebn0", [2.5, 3.5, 4.5])
+def test_ber_gap_ml_reference_is_ml(dev, ebn0):
+    # bench.py's BER-gap grids take the blocked decoder with v1 = v2 = 128 as
+    # the maximum-likelihood reference; on the first 2^18 bits of each of its
+    # streams (same seeds) it agrees with the oracle's full-frame ML decode of
+    # that prefix as an open stream, except where the prefix end is unknown
+    # (the last 64 bits) and for a handful of bits at the lowest Eb/N0
+    torch, vit = dev
+    k, gens = CODES["k7r12"]
+    n = 1 << 24
+    bits, llr = synth.make_stream("k7r12", n, ebn0, seed=100 + int(ebn0 * 10))
+    got = synth.unpack_bits(_gpu(dev, k, gens, llr, n, 512, 256, v1=128), n)
+    m = 1 << 18
+    ref = vref.decode_full(vref.make_code(k, list(gens)), llr[: m * 2], m, terminated=False)
+    diff = int(np.sum(ref[: m - 64] != got[: m - 64]))
+    print(f"Eb/N0 {ebn0}: {diff} bits differ from full-frame ML")
+    assert diff <= (64 if ebn0 < 3.0 else 0)

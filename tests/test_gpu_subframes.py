@@ -1,8 +1,8 @@
 """The subframe traceback (Sec. IV-D) on the GPU against the oracle's
-two-subframe decoder, bit for bit: each block's trace split into an upper
-chain from the block end and a lower chain from the best state at a survivor
-word boundary, with W words of inner overlap.  The survivor word length is
-(k-1)*floor(32/(k-1)) stages, as the decoder's ABI documents."""
+subframe decoder, bit for bit: each block's trace cut into subframes of F
+survivor words, each traced by its own chain from the best state W words
+above its subframe.  The survivor word length is (k-1)*floor(32/(k-1))
+stages, as the decoder's ABI documents."""
 import os
 
 import numpy as np
@@ -39,12 +39,13 @@ def dev():
     return torch, vit
 
 
-def _check(dev, k, gens, llr, n, L, v, W, v1=None, terminated=True, plain_equal=False):
+def _check(dev, k, gens, llr, n, L, v, F, W, v1=None, terminated=True, plain_equal=False):
     torch, vit = dev
-    print(f"[gpu] k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} W={W} term={terminated} "
+    print(f"[gpu] k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} F={F} W={W} term={terminated} "
           f"dtype={llr.dtype}", flush=True)
     t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
-    got = vit.decode(vit.make_code(k, gens), t, n, L, v, v1=v1, terminated=terminated, subframe_overlap=W)
+    got = vit.decode(vit.make_code(k, gens), t, n, L, v, v1=v1, terminated=terminated, subframe_words=F,
+                     subframe_overlap=W)
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     e1 = v // 2 if v1 is None else v1
@@ -55,7 +56,7 @@ def _check(dev, k, gens, llr, n, L, v, W, v1=None, terminated=True, plain_equal=
     Lb, e2 = L, v - e1
     if L == 0:  # the full frame is one block reaching the last stage (tail included)
         Lb, e1, e2 = n, 0, k - 1 if terminated else 0
-    want = synth.pack_bits(vref.decode_blocked_split(code, ol, n, Lb, e1, e2, word_stages(k), W, terminated,
+    want = synth.pack_bits(vref.decode_blocked_split(code, ol, n, Lb, e1, e2, word_stages(k), F, W, terminated,
                                                      nthreads=NCPU))
     if not np.array_equal(got, want):
         gb, wb = synth.unpack_bits(got, n), synth.unpack_bits(want, n)
@@ -79,36 +80,38 @@ GEOMS = [
     (1000, 0, 0, None, True), (1000, 0, 0, None, False), (1001, 128, 35, 30, True), (3333, 64, 12, 12, False),
     (6144, 256, 35, None, True), (6144, 1024, 45, None, True), (777, 8, 60, None, True), (5000, 512, 64, 20, True),
 ]
+SPLITS = [(1, 0), (1, 2), (2, 1), (3, 5)]
 
 
 @pytest.mark.parametrize("name", list(CODES))
 @pytest.mark.parametrize("n,L,v,v1,terminated", GEOMS)
-@pytest.mark.parametrize("W", [0, 2])
-def test_geometry_sweep_awgn(dev, name, n, L, v, v1, terminated, W):
+@pytest.mark.parametrize("F,W", SPLITS)
+def test_geometry_sweep_awgn(dev, name, n, L, v, v1, terminated, F, W):
     k, gens = CODES[name]
-    _, llr = _awgn(k, gens, n, 1.0, seed=n * 17 + L + v + W, terminated=terminated)
-    _check(dev, k, gens, llr, n, L, v, W, v1, terminated)
+    _, llr = _awgn(k, gens, n, 1.0, seed=n * 17 + L + v + 7 * F + W, terminated=terminated)
+    _check(dev, k, gens, llr, n, L, v, F, W, v1, terminated)
 
 
 @pytest.mark.parametrize("name", list(CODES))
 def test_integer_llrs_with_ties(dev, name):
-    # ties in the survivor choices and in the best state at the split
+    # ties in the survivor choices and in the best states at subframe starts
     k, gens = CODES[name]
     rng = np.random.default_rng(15)
-    for (n, L, v, W, terminated) in ((900, 256, 10, 0, True), (900, 0, 0, 1, False), (600, 128, 40, 1, True)):
+    for (n, L, v, F, W, terminated) in ((900, 256, 10, 1, 0, True), (900, 0, 0, 2, 1, False),
+                                        (600, 128, 40, 1, 1, True)):
         N = n + (k - 1 if terminated else 0)
         llr = synth.integer_llr(N * len(gens), -2, 2, rng)
-        _check(dev, k, gens, llr, n, L, v, W, None, terminated)
+        _check(dev, k, gens, llr, n, L, v, F, W, None, terminated)
 
 
 @pytest.mark.parametrize("name", ["k7r12", "k7r13", "k9r12", "k5r12x"])
 def test_all_zero_llrs(dev, name):
-    # every metric ties: both chains start from state 0 by the tie rule
+    # every metric ties: every chain starts from state 0 by the tie rule
     k, gens = CODES[name]
     n = 2000
     llr = np.zeros((n + k - 1) * len(gens), dtype=np.float32)
-    _check(dev, k, gens, llr, n, 512, 40, 0)
-    _check(dev, k, gens, llr, n, 0, 0, 1)
+    _check(dev, k, gens, llr, n, 512, 40, 1, 0)
+    _check(dev, k, gens, llr, n, 0, 0, 40, 1)
 
 
 @pytest.mark.parametrize("name", ["k7r12", "k7r13", "k9r12", "k4r14"])
@@ -116,24 +119,31 @@ def test_int8_and_hard_inputs(dev, name):
     k, gens = CODES[name]
     bits, llr = _awgn(k, gens, 20000, 2.0, seed=23)
     q = vref.quantize_i8(llr, 4.0)
-    _check(dev, k, gens, q, 20000, 512, 40, 1)
+    _check(dev, k, gens, q, 20000, 512, 40, 2, 1)
     hard = (llr < 0).astype(np.uint8)
-    _check(dev, k, gens, hard, 20000, 256, 42, 2)
+    _check(dev, k, gens, hard, 20000, 256, 42, 1, 2)
 
 
-def test_without_room_is_the_plain_decoder(dev):
-    # W so large that no block splits: identical to the one-trace decode
+def test_one_subframe_is_the_plain_decoder(dev):
+    # F so large that every block has one subframe: identical to the one-trace decode
     k, gens = CODES["k7r12"]
     _, llr = _awgn(k, gens, 30000, 1.5, seed=3)
-    _check(dev, k, gens, llr, 30000, 512, 35, 1000, plain_equal=True)
+    _check(dev, k, gens, llr, 30000, 512, 35, 1000, 2, plain_equal=True)
 
 
-@pytest.mark.parametrize("W", [0, 2])
-def test_full_size_stream_k7(dev, W):
+def test_most_subframes(dev):
+    # 64 subframes of one word: a full frame of 1914 bits + 6 tail stages
+    k, gens = CODES["k7r12"]
+    _, llr = _awgn(k, gens, 1914, 2.0, seed=5)
+    _check(dev, k, gens, llr, 1914, 0, 0, 1, 1)
+
+
+@pytest.mark.parametrize("F,W", [(1, 1), (4, 2)])
+def test_full_size_stream_k7(dev, F, W):
     # the 2^24-bit throughput stream in the benchmark's launch configuration
     # (L = 512, v = 35); the oracle decodes it completely (all host cores)
     k, gens = CODES["k7r12"]
     n = 1 << 24
     bits, llr = synth.make_stream("k7r12", n, 3.0, seed=1 + 3)
-    got = _check(dev, k, gens, llr, n, 512, 35, W)
-    print(f"full size W={W}: BER {np.mean(got != bits):.3e}")
+    got = _check(dev, k, gens, llr, n, 512, 35, F, W)
+    print(f"full size F={F} W={W}: BER {np.mean(got != bits):.3e}")
