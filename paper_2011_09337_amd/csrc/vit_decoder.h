@@ -160,7 +160,7 @@ __device__ __forceinline__ void flush_decision(uint32_t &d, uint64_t &pend) {
 
 template <int Q, bool NEG, bool STD>
 __device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, uint64_t &pend, float s, float c,
-                                         float y, int xor32_addr) {
+                                         float y) {
   float B;
   if constexpr (Q < 4) {
 #define VIT_DISPATCH_DPP(DPPSTR)                                                            \
@@ -175,7 +175,6 @@ __device__ __forceinline__ void acs_lane(float &o, float &x, uint32_t &d, uint64
     else { VIT_DISPATCH_DPP(VIT_DPP_Q3) }
 #undef VIT_DISPATCH_DPP
   } else {
-    (void)xor32_addr;
     if constexpr (Q == 4) {
       if constexpr (STD) {
         if constexpr (NEG) VIT_ACS_PERM("v_permlane16_swap_b32", "-", "-%[x]");
@@ -243,7 +242,6 @@ struct Decoder {
   int lane;
   bool hard;             // byte inputs are hard decisions (0 / nonzero), not int8 LLRs
   int slot0;             // slot index of register 0 in this lane
-  int xor32_addr;        // ds_bpermute byte address of lane ^ 32
   uint32_t own_mask[REGS];  // per body offset: bit q of this slot's index (traceback encoding)
 
   // per-block state
@@ -282,7 +280,6 @@ struct Decoder {
   __device__ __forceinline__ void setup(const uint32_t *gen) {
     lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     slot0 = lane ^ (((lane >> 2) & 1) ? 3 : 0);  // inverse of the lane_vec map
-    xor32_addr = (lane ^ 32) << 2;
     tl = lane >> BETA;
     const int pat = lane & (NCODE - 1);
 #pragma unroll
@@ -530,8 +527,8 @@ struct Decoder {
 #pragma unroll
     for (int r = 0; r < REGS; ++r) {
       if (r == reg) {
-        if (reg_neg<P>(Q, r)) acs_lane<Q, true, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y, xor32_addr);
-        else acs_lane<Q, false, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y, xor32_addr);
+        if (reg_neg<P>(Q, r)) acs_lane<Q, true, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y);
+        else acs_lane<Q, false, STD>(o[r], x, dec[r], pend[r], sgn[Q], cmed[Q], y);
       }
     }
   }
