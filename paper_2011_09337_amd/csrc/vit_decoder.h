@@ -745,12 +745,13 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
   }
 }
 
-// For 5 <= k <= 7 the register budget is held to 64 VGPRs (eight waves per
-// SIMD): left to itself the scheduler trades occupancy for deeper prefetch of
-// branch metrics in some instances; the few scalar spills this costs are in
-// the block prologue.
+// For 5 <= k <= 7 the one-trace instances are held to 64 VGPRs (eight waves
+// per SIMD): left to itself the scheduler trades occupancy for deeper
+// prefetch of branch metrics in some instances; the few scalar spills this
+// costs are in the block prologue.  (The subframe instances would spill
+// vector registers under the same bound.)
 template <int K, int BETA, bool STD, bool I8, bool SUB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 5 && K <= 7 ? 8 : 1, 8))) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SUB && K >= 5 && K <= 7 ? 8 : 1, 8))) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, I8>;
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
