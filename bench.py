@@ -49,6 +49,8 @@ def parse():
                     help="headline decode with the subframe traceback: F words per subframe, W words of overlap")
     ap.add_argument("--no-subframe-probe", action="store_true",
                     help="skip the side measurement of the subframe traceback")
+    ap.add_argument("--precision", action="store_true",
+                    help="print the int8-vs-FP32 BER sweep (three codes, 0..6 dB) and exit")
     ap.add_argument("--table3", action="store_true",
                     help="print the BER-gap grid of the subframe traceback (F x W) and exit")
     ap.add_argument("--no-cpu", action="store_true")
@@ -450,6 +452,56 @@ def ber_gaps(vit, torch, configs, log2n=24):
     }
 
 
+def precision_sweep(vit, torch, log2n=24):
+    """The integer path's cost: the same 2^log2n-bit stream for K=7 r1/2, K=7
+    r1/3 and K=9 r1/2 at Eb/N0 0..6 dB, decoded from FP32 LLRs and from int8
+    LLRs (quantised on the GPU with the per-Eb/N0 scale: a noiseless symbol
+    maps to 8), BER of each, the Eb/N0 each needs for BER 1e-4 (log-linear
+    interpolation) and their difference, and both paths' stream throughput at
+    3 dB.  Block shapes: L=512, v=35 for K=7; L=256, v=45 for K=9."""
+    import numpy as np
+    import synth
+    n = 1 << log2n
+    grid = list(range(7))
+    res = {}
+    out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
+    for name, (L, v) in (("k7r12", (512, 35)), ("k7r13", (512, 35)), ("k9r12", (256, 45))):
+        k, gens = synth.CODES[name]
+        code = vit.make_code(k, gens)
+        rows = {"fp32": [], "int8": []}
+        mbps = {}
+        for e in grid:
+            bits, llr = synth.make_stream(name, n, float(e), seed=1 + e)
+            d = torch.from_numpy(llr).cuda()
+            q = vit.quantize(d, 8.0 * synth.noise_sigma(float(e), len(gens)) ** 2 / 2.0)
+            for tag, x in (("fp32", d), ("int8", q)):
+                vit.decode(code, x, n, L, v, out=out)
+                got = synth.unpack_bits(out.cpu().numpy(), n)
+                rows[tag].append(int(np.sum(got != bits)))
+                if e == 3:
+                    ms, _ = time_decode(vit, torch, code, x, out, n, L, v, 10, 2)
+                    mbps[tag] = round(n / (ms * 1e-3) / 1e6, 1)
+            print(f"[precision] {name} {e} dB done", file=sys.stderr, flush=True)
+
+        def at_1e4(errs):
+            bers = [max(x, 0.5) / n for x in errs]
+            for i in range(len(grid) - 1):
+                if bers[i] >= 1e-4 > bers[i + 1]:
+                    y0, y1 = np.log(bers[i]), np.log(bers[i + 1])
+                    return grid[i] + (np.log(1e-4) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
+            return None
+
+        af, aq = at_1e4(rows["fp32"]), at_1e4(rows["int8"])
+        res[name] = {"L": L, "v": v, "ebn0_db": grid,
+                     "ber_fp32": [x / n for x in rows["fp32"]], "ber_int8": [x / n for x in rows["int8"]],
+                     "ebn0_at_1e-4_fp32": None if af is None else round(float(af), 4),
+                     "ebn0_at_1e-4_int8": None if aq is None else round(float(aq), 4),
+                     "int8_loss_db": None if af is None or aq is None else round(float(aq - af), 4),
+                     "mbps_at_3db": mbps}
+    return {"workload": f"2^{log2n}-bit terminated streams, BPSK/AWGN, seed 1 + Eb/N0; int8 scale 8 sigma^2 / 2",
+            "codes": res}
+
+
 def table2_configs():
     """The paper's Table II grid: f = L in {32..512}, v2 in {10..40}, v1 = v2."""
     return {f"v2={v2},f={f}": dict(L=f, v1=v2, v2=v2) for v2 in (10, 20, 30, 40) for f in (32, 64, 128, 256, 512)}
@@ -483,6 +535,9 @@ def main():
         return
     if args.table3:
         print(json.dumps({"table3": ber_gaps(vit, torch, table3_configs())}), flush=True)
+        return
+    if args.precision:
+        print(json.dumps({"precision": precision_sweep(vit, torch)}), flush=True)
         return
 
     head_sub = None if args.subframes is None else tuple(int(x) for x in args.subframes.split(":"))
@@ -519,6 +574,11 @@ def main():
     torch.cuda.synchronize()
     got = synth.unpack_bits(out_d.cpu().numpy(), n)
     ber = float(np.mean(got != bits))
+    # bit difference from maximum likelihood: the blocked decoder with
+    # v1 = v2 = 128 stands for it (tests check it against full-frame ML)
+    vit.decode(code, llr_d, n, 512, 256, v1=128, out=out_d)
+    torch.cuda.synchronize()
+    vs_ml = int(np.sum(synth.unpack_bits(out_d.cpu().numpy(), n) != got))
     # side measurement: one trace per block vs subframes (Sec. IV-D)
     subframe = None
     if not args.no_subframe_probe:
@@ -585,6 +645,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ber": ber,
+        "bits_differing_from_ml": vs_ml,
         "subframe_traceback": subframe,
         "batched": batched,
         "serving": serving,
