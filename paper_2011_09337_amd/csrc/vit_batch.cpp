@@ -380,7 +380,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     for (int c = 0; c < ncodes; ++c) {
       int unsupported = 0;
       const char *why = "";
-      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type != VIT_LLR_F32,
+      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type,
                                   (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &bl[c], &unsupported,
                                   &why);
       if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
@@ -399,7 +399,6 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
       args.header = (int32_t *)workspace;
       args.items = (const WorkItem *)((char *)workspace + kHeaderBytes);
       args.code_index = c;
-      args.hard = llr_type == VIT_LLR_HARD ? 1 : 0;
       for (int b = 0; b < 4; ++b) args.gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0u;
       int words = bl[c].lds_words_per_wave;
       void *kargs[] = {&args, &words};

@@ -224,8 +224,12 @@ __device__ __forceinline__ uint32_t select_reg(const uint32_t (&v)[REGS], uint32
   return t[rsel & (REGS - 1)];
 }
 
-template <int K, int BETA, bool STD, bool I8>
+// IN: input kind, VIT_LLR_F32 (float LLRs), VIT_LLR_I8 (int8 LLRs) or
+// VIT_LLR_HARD (hard-decision bytes), fixed per kernel instance.
+template <int K, int BETA, bool STD, int IN>
 struct Decoder {
+  static constexpr bool I8 = IN != VIT_LLR_F32;       // one byte per value
+  static constexpr bool HARD = IN == VIT_LLR_HARD;
   using Sh = Shape<K, BETA>;
   static constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, NCODE = Sh::NCODE, T = Sh::T,
                        BODY = Sh::BODY;
@@ -240,7 +244,6 @@ struct Decoder {
   float bsign[BETA];     // signs of this lane's output pattern in the metric table
   int tl;                // stage of this lane's metric table entry within a tile
   int lane;
-  bool hard;             // byte inputs are hard decisions (0 / nonzero), not int8 LLRs
   int slot0;             // slot index of register 0 in this lane
   uint32_t own_mask[REGS];  // per body offset: bit q of this slot's index (traceback encoding)
 
@@ -339,7 +342,7 @@ struct Decoder {
   // fma with a +-1 multiplier rounds exactly like the plain add.
   __device__ __forceinline__ float llr_value(int raw) const {
     if constexpr (I8) {
-      if (hard) return raw == 0 ? 1.0f : -1.0f;  // hard decision: coded bit 0 -> +1, 1 -> -1
+      if constexpr (HARD) return raw == 0 ? 1.0f : -1.0f;  // hard decision: coded bit 0 -> +1, 1 -> -1
       return (float)raw;                         // exact: |int8| <= 128
     } else {
       return __builtin_bit_cast(float, raw);
@@ -571,8 +574,8 @@ struct Decoder {
 // (Sec. IV-D); others trace each block once (and ignore both).  Stages are
 // frame-local; the caller guarantees (e - s) * beta * sizeof(LLR) < 2^31, cs
 // a multiple of 8, and at most 64 subframes per block.
-template <bool SUB, int K, int BETA, bool STD, bool I8>
-__device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const void *llr, uint8_t *out,
+template <bool SUB, int K, int BETA, bool STD, int IN>
+__device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, IN> &D, const void *llr, uint8_t *out,
                                              int64_t s, int64_t e, int64_t cs, int64_t ce, bool start_known,
                                              bool end_zero, int tb_words, int tb_overlap, const uint32_t *gen) {
   using Sh = Shape<K, BETA>;
@@ -750,9 +753,9 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, I8> &D, const
 // prefetch of branch metrics in some instances; the few scalar spills this
 // costs are in the block prologue.  (The subframe instances would spill
 // vector registers under the same bound.)
-template <int K, int BETA, bool STD, bool I8, bool SUB>
+template <int K, int BETA, bool STD, int IN, bool SUB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SUB && K >= 5 && K <= 7 ? 8 : 1, 8))) void vit_blocked_kernel(DecodeArgs a, int lds_words_per_wave) {
-  using Dec = Decoder<K, BETA, STD, I8>;
+  using Dec = Decoder<K, BETA, STD, IN>;
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
   static_assert(BODY <= 32, "unrolled body longer than one decision dword");
@@ -760,7 +763,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SUB && K >
 
   Dec D;
   D.setup(a.gen);
-  D.hard = a.llr_type == VIT_LLR_HARD;
   // wave index and count are uniform across the wave: keep them scalar
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
@@ -804,13 +806,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SUB && K >
 // code's run live in the workspace header.  For standard codes up to k = 7
 // the register budget is held to 64 VGPRs (eight waves per SIMD, as the
 // stream kernel).
-template <int K, int BETA, bool STD, bool I8>
+template <int K, int BETA, bool STD, int IN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <= 7 ? 8 : 1, 8))) void vit_batch_kernel(BatchArgs a, int lds_words_per_wave) {
-  using Dec = Decoder<K, BETA, STD, I8>;
+  using Dec = Decoder<K, BETA, STD, IN>;
   extern __shared__ uint32_t vit_lds[];
   Dec D;
   D.setup(a.gen);
-  D.hard = a.hard != 0;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
   D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
@@ -835,14 +836,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
 typedef void (*KernelFn)(DecodeArgs, int);
 typedef void (*BatchKernelFn)(BatchArgs, int);
 
-// Kernel instance for (K, beta, standard code, int8 input, subframe traceback).
+// Kernel instance for (K, beta, standard code, input kind, subframe traceback).
 template <int K, bool SUB>
-KernelFn pick_kernel_k(int beta, bool stdc, bool i8) {
+KernelFn pick_kernel_k(int beta, bool stdc, int in) {
   auto pick = [&](auto bt) -> KernelFn {
     constexpr int B = decltype(bt)::value;
-    if (stdc)
-      return i8 ? dev::vit_blocked_kernel<K, B, true, true, SUB> : dev::vit_blocked_kernel<K, B, true, false, SUB>;
-    return i8 ? dev::vit_blocked_kernel<K, B, false, true, SUB> : dev::vit_blocked_kernel<K, B, false, false, SUB>;
+    if (stdc) {
+      if (in == VIT_LLR_HARD) return dev::vit_blocked_kernel<K, B, true, VIT_LLR_HARD, SUB>;
+      return in == VIT_LLR_I8 ? dev::vit_blocked_kernel<K, B, true, VIT_LLR_I8, SUB>
+                              : dev::vit_blocked_kernel<K, B, true, VIT_LLR_F32, SUB>;
+    }
+    if (in == VIT_LLR_HARD) return dev::vit_blocked_kernel<K, B, false, VIT_LLR_HARD, SUB>;
+    return in == VIT_LLR_I8 ? dev::vit_blocked_kernel<K, B, false, VIT_LLR_I8, SUB>
+                            : dev::vit_blocked_kernel<K, B, false, VIT_LLR_F32, SUB>;
   };
   switch (beta) {
     case 2: return pick(std::integral_constant<int, 2>{});
@@ -853,11 +859,15 @@ KernelFn pick_kernel_k(int beta, bool stdc, bool i8) {
 }
 
 template <int K>
-BatchKernelFn pick_batch_kernel_k(int beta, bool stdc, bool i8) {
+BatchKernelFn pick_batch_kernel_k(int beta, bool stdc, int in) {
   auto pick = [&](auto bt) -> BatchKernelFn {
     constexpr int B = decltype(bt)::value;
-    if (stdc) return i8 ? dev::vit_batch_kernel<K, B, true, true> : dev::vit_batch_kernel<K, B, true, false>;
-    return i8 ? dev::vit_batch_kernel<K, B, false, true> : dev::vit_batch_kernel<K, B, false, false>;
+    if (stdc) {
+      if (in == VIT_LLR_HARD) return dev::vit_batch_kernel<K, B, true, VIT_LLR_HARD>;
+      return in == VIT_LLR_I8 ? dev::vit_batch_kernel<K, B, true, VIT_LLR_I8> : dev::vit_batch_kernel<K, B, true, VIT_LLR_F32>;
+    }
+    if (in == VIT_LLR_HARD) return dev::vit_batch_kernel<K, B, false, VIT_LLR_HARD>;
+    return in == VIT_LLR_I8 ? dev::vit_batch_kernel<K, B, false, VIT_LLR_I8> : dev::vit_batch_kernel<K, B, false, VIT_LLR_F32>;
   };
   switch (beta) {
     case 2: return pick(std::integral_constant<int, 2>{});
@@ -867,26 +877,26 @@ BatchKernelFn pick_batch_kernel_k(int beta, bool stdc, bool i8) {
   return nullptr;
 }
 
-KernelFn pick_kernel_k3(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k3(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k4(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k4(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k5(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k5(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k6(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k6(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k7(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k7(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k8(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k8(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_k9(int beta, bool stdc, bool i8);
-KernelFn pick_kernel_sub_k9(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k4(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k5(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k6(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k7(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k8(int beta, bool stdc, bool i8);
-BatchKernelFn pick_batch_kernel_k9(int beta, bool stdc, bool i8);
+KernelFn pick_kernel_k3(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k3(int beta, bool stdc, int in);
+KernelFn pick_kernel_k4(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k4(int beta, bool stdc, int in);
+KernelFn pick_kernel_k5(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k5(int beta, bool stdc, int in);
+KernelFn pick_kernel_k6(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k6(int beta, bool stdc, int in);
+KernelFn pick_kernel_k7(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k7(int beta, bool stdc, int in);
+KernelFn pick_kernel_k8(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k8(int beta, bool stdc, int in);
+KernelFn pick_kernel_k9(int beta, bool stdc, int in);
+KernelFn pick_kernel_sub_k9(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k4(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k5(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k6(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k7(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k8(int beta, bool stdc, int in);
+BatchKernelFn pick_batch_kernel_k9(int beta, bool stdc, int in);
 
 }  // namespace vit

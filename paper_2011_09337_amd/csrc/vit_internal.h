@@ -51,7 +51,6 @@ struct BatchArgs {
   int32_t *header;           // device, workspace header
   const WorkItem *items;     // device, all work items (each code's run is cost-descending)
   int32_t code_index;
-  int32_t hard;              // 1: one byte per coded bit, 0 / nonzero -> LLR +1 / -1
   uint32_t gen[4];
 };
 
@@ -76,7 +75,7 @@ struct BatchLaunch {
 // Fill *bl for a code (k, beta, generators, int8?) decoding blocks of at most
 // max_block_stages stages with `wpb` waves per workgroup.  Returns hipSuccess;
 // sets *unsupported when the shape is not available.
-hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, bool i8, int64_t max_block_stages, int wpb,
+hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, int in, int64_t max_block_stages, int wpb,
                              BatchLaunch *bl, int *unsupported, const char **why);
 
 // Error reporting shared by the C ABI translation units (thread-local message).

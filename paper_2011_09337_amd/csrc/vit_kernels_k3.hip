@@ -2,6 +2,6 @@
 #include "vit_decoder.h"
 
 namespace vit {
-KernelFn pick_kernel_k3(int beta, bool stdc, bool i8) { return pick_kernel_k<3, false>(beta, stdc, i8); }
-BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, bool i8) { return pick_batch_kernel_k<3>(beta, stdc, i8); }
+KernelFn pick_kernel_k3(int beta, bool stdc, int in) { return pick_kernel_k<3, false>(beta, stdc, in); }
+BatchKernelFn pick_batch_kernel_k3(int beta, bool stdc, int in) { return pick_batch_kernel_k<3>(beta, stdc, in); }
 }  // namespace vit

@@ -2,5 +2,5 @@
 #include "vit_decoder.h"
 
 namespace vit {
-KernelFn pick_kernel_sub_k9(int beta, bool stdc, bool i8) { return pick_kernel_k<9, true>(beta, stdc, i8); }
+KernelFn pick_kernel_sub_k9(int beta, bool stdc, int in) { return pick_kernel_k<9, true>(beta, stdc, in); }
 }  // namespace vit

@@ -6,15 +6,15 @@ namespace vit {
 namespace {
 
 
-KernelFn pick_kernel(int k, int beta, bool stdc, bool i8, bool sub) {
+KernelFn pick_kernel(int k, int beta, bool stdc, int in, bool sub) {
   switch (k) {
-    case 3: return sub ? pick_kernel_sub_k3(beta, stdc, i8) : pick_kernel_k3(beta, stdc, i8);
-    case 4: return sub ? pick_kernel_sub_k4(beta, stdc, i8) : pick_kernel_k4(beta, stdc, i8);
-    case 5: return sub ? pick_kernel_sub_k5(beta, stdc, i8) : pick_kernel_k5(beta, stdc, i8);
-    case 6: return sub ? pick_kernel_sub_k6(beta, stdc, i8) : pick_kernel_k6(beta, stdc, i8);
-    case 7: return sub ? pick_kernel_sub_k7(beta, stdc, i8) : pick_kernel_k7(beta, stdc, i8);
-    case 8: return sub ? pick_kernel_sub_k8(beta, stdc, i8) : pick_kernel_k8(beta, stdc, i8);
-    case 9: return sub ? pick_kernel_sub_k9(beta, stdc, i8) : pick_kernel_k9(beta, stdc, i8);
+    case 3: return sub ? pick_kernel_sub_k3(beta, stdc, in) : pick_kernel_k3(beta, stdc, in);
+    case 4: return sub ? pick_kernel_sub_k4(beta, stdc, in) : pick_kernel_k4(beta, stdc, in);
+    case 5: return sub ? pick_kernel_sub_k5(beta, stdc, in) : pick_kernel_k5(beta, stdc, in);
+    case 6: return sub ? pick_kernel_sub_k6(beta, stdc, in) : pick_kernel_k6(beta, stdc, in);
+    case 7: return sub ? pick_kernel_sub_k7(beta, stdc, in) : pick_kernel_k7(beta, stdc, in);
+    case 8: return sub ? pick_kernel_sub_k8(beta, stdc, in) : pick_kernel_k8(beta, stdc, in);
+    case 9: return sub ? pick_kernel_sub_k9(beta, stdc, in) : pick_kernel_k9(beta, stdc, in);
   }
   return nullptr;
 }
@@ -45,7 +45,7 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   *unsupported = 0;
   bool stdc = true;
   for (int b = 0; b < a.beta; ++b) stdc = stdc && ((a.gen[b] >> (a.k - 1)) & 1u) && (a.gen[b] & 1u);
-  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type != VIT_LLR_F32, a.tb_words > 0);
+  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type, a.tb_words > 0);
   if (!fn) {
     *unsupported = 1;
     *why = "no kernel instance for this (k, beta)";
@@ -94,20 +94,20 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   return hipGetLastError();
 }
 
-hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, bool i8, int64_t max_block_stages, int wpb,
+hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, int in, int64_t max_block_stages, int wpb,
                              BatchLaunch *bl, int *unsupported, const char **why) {
   *unsupported = 0;
   bool stdc = true;
   for (int b = 0; b < beta; ++b) stdc = stdc && ((gen[b] >> (k - 1)) & 1u) && (gen[b] & 1u);
   BatchKernelFn fn = nullptr;
   switch (k) {
-    case 3: fn = pick_batch_kernel_k3(beta, stdc, i8); break;
-    case 4: fn = pick_batch_kernel_k4(beta, stdc, i8); break;
-    case 5: fn = pick_batch_kernel_k5(beta, stdc, i8); break;
-    case 6: fn = pick_batch_kernel_k6(beta, stdc, i8); break;
-    case 7: fn = pick_batch_kernel_k7(beta, stdc, i8); break;
-    case 8: fn = pick_batch_kernel_k8(beta, stdc, i8); break;
-    case 9: fn = pick_batch_kernel_k9(beta, stdc, i8); break;
+    case 3: fn = pick_batch_kernel_k3(beta, stdc, in); break;
+    case 4: fn = pick_batch_kernel_k4(beta, stdc, in); break;
+    case 5: fn = pick_batch_kernel_k5(beta, stdc, in); break;
+    case 6: fn = pick_batch_kernel_k6(beta, stdc, in); break;
+    case 7: fn = pick_batch_kernel_k7(beta, stdc, in); break;
+    case 8: fn = pick_batch_kernel_k8(beta, stdc, in); break;
+    case 9: fn = pick_batch_kernel_k9(beta, stdc, in); break;
   }
   if (!fn) {
     *unsupported = 1;

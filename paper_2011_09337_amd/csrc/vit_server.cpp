@@ -196,7 +196,6 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     a.header = (int32_t *)wsd;
     a.items = (const vit::WorkItem *)(wsd + kHeaderBytes);
     a.code_index = c;
-    a.hard = s->llr_type == VIT_LLR_HARD ? 1 : 0;
     for (int b = 0; b < 4; ++b) a.gen[b] = b < s->codes[c].beta ? s->codes[c].gen[b] : 0u;
     int words = s->bl[c].lds_words_per_wave;
     void *kargs[] = {&a, &words};
@@ -433,7 +432,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
     s->shape[c] = shape[c];
     int unsupported = 0;
     const char *why = "";
-    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type != VIT_LLR_F32,
+    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type,
                                (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &s->bl[c], &unsupported,
                                &why);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "batch launch planning"));
