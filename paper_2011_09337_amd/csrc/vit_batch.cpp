@@ -392,7 +392,17 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     he = hipGraphAddMemcpyNode1D(&plan->copy_node, plan->graph, nullptr, 0, workspace, stg, need,
                                  hipMemcpyHostToDevice);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddMemcpyNode1D");
-    for (int c = 0; c < ncodes; ++c) {
+    // one kernel node per code, run one after another, the code with the
+    // most work per bit (states x rate) first: measured faster than running
+    // them side by side
+    int order[kMaxCodes];
+    for (int c = 0; c < ncodes; ++c) order[c] = c;
+    std::stable_sort(order, order + ncodes, [&](int x, int y) {
+      return ((int64_t)codes[x].beta << (codes[x].k - 1)) > ((int64_t)codes[y].beta << (codes[y].k - 1));
+    });
+    hipGraphNode_t prev = plan->copy_node;
+    for (int oi = 0; oi < ncodes; ++oi) {
+      const int c = order[oi];
       vit::BatchArgs args;
       args.llr = llr;
       args.out = out;
@@ -411,8 +421,9 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
       kp.kernelParams = kargs;
       kp.extra = nullptr;
       hipGraphNode_t kn;
-      he = hipGraphAddKernelNode(&kn, plan->graph, &plan->copy_node, 1, &kp);
+      he = hipGraphAddKernelNode(&kn, plan->graph, &prev, 1, &kp);
       if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddKernelNode");
+      prev = kn;
     }
     he = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphInstantiate");
