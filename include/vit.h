@@ -163,8 +163,9 @@ int vit_query_geometry(const vit_code *code, int64_t n, int32_t L, int32_t v, in
 /* ---------------------------------------------------------------- batches
  * Many independent frames (each its own stream, Sec. III applied per frame),
  * possibly of different codes and lengths, decoded by one graph launch: one
- * persistent kernel per code walks the frames' blocks in a cost-sorted work
- * list (longest first), wave w of W taking items w, w + W, w + 2W, ...
+ * persistent kernel per code (in sequence, most work per bit first) walks the
+ * frames' blocks in a cost-sorted work list (longest first), wave w of W
+ * taking items w, w + W, w + 2W, ...
  * Results are identical, bit for bit, to decoding each frame alone with
  * vit_decode_ex and the same (L, v, v1). */
 

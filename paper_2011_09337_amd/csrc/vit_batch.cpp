@@ -5,10 +5,10 @@
 // (Sec. III of the paper, per frame).  Each block is one work item; items of
 // one code are sorted by cost (stages) so the persistent waves of that code's
 // kernel take the longest first.  Per call the host writes the header (item
-// counters = 0, counts, offsets) and the items into pinned staging memory; the
-// graph copies them into the caller's device workspace and runs one kernel
-// node per code.  While the buffers, codes and shapes stay the same the graph
-// is reused and only its copy node is updated.
+// counts and run offsets per code) and the items into pinned staging memory;
+// the graph copies them into the caller's device workspace and runs one kernel
+// node per code, in sequence.  While the buffers, codes and shapes stay the
+// same the graph is reused and only its copy node is updated.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
