@@ -88,6 +88,16 @@ __global__ __launch_bounds__(256) void mb(float *out, int iters) {
       if constexpr (V == 25)
         asm volatile("v_cndmask_b32 %[a], %[a], %[b], %[m]\n v_cndmask_b32 %[b], %[b], %[c], %[m]\n v_cndmask_b32 %[c], %[c], %[d], %[m]\n v_cndmask_b32 %[d], %[d], %[e], %[m]\n v_cndmask_b32 %[e], %[e], %[f], %[m]\n v_cndmask_b32 %[f], %[f], %[a], %[m]\n"
                      : [a] "+v"(u0), [b] "+v"(u1), [c] "+v"(u2), [d] "+v"(u3), [e] "+v"(u4), [f] "+v"(u5) : [m] "s"(m));
+      if constexpr (V == 26) {  // lane reads into SGPRs (the traceback's step)
+        uint32_t r0, r1, r2, r3, r4, r5;
+        asm volatile("v_readlane_b32 %[r0], %[a], 5\n v_readlane_b32 %[r1], %[b], 9\n v_readlane_b32 %[r2], %[c], 17\n v_readlane_b32 %[r3], %[d], 33\n v_readlane_b32 %[r4], %[e], 40\n v_readlane_b32 %[r5], %[f], 63\n"
+                     : [r0] "=s"(r0), [r1] "=s"(r1), [r2] "=s"(r2), [r3] "=s"(r3), [r4] "=s"(r4), [r5] "=s"(r5)
+                     : [a] "v"(u0), [b] "v"(u1), [c] "v"(u2), [d] "v"(u3), [e] "v"(u4), [f] "v"(u5));
+        m += r0 ^ r1 ^ r2 ^ r3 ^ r4 ^ r5;
+      }
+      if constexpr (V == 27)  // lane writes from an SGPR
+        asm volatile("v_writelane_b32 %[a], %[m], 5\n v_writelane_b32 %[b], %[m], 9\n v_writelane_b32 %[c], %[m], 17\n v_writelane_b32 %[d], %[m], 33\n v_writelane_b32 %[e], %[m], 40\n v_writelane_b32 %[f], %[m], 63\n"
+                     : [a] "+v"(u0), [b] "+v"(u1), [c] "+v"(u2), [d] "+v"(u3), [e] "+v"(u4), [f] "+v"(u5) : [m] "s"((uint32_t)m));
     }
   }
   out[blockIdx.x * blockDim.x + threadIdx.x] = a + b + c + d + e + f + (float)(u0 + u1 + u2 + u3 + u4 + u5) + (float)(m & 1);
@@ -104,9 +114,9 @@ int main() {
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  K ks[] = {mb<0>, mb<1>, mb<2>, mb<3>, mb<4>, mb<5>, mb<6>, mb<7>, mb<8>, mb<9>, mb<10>, mb<11>, mb<12>, mb<13>, mb<14>, mb<15>, mb<16>, mb<17>, mb<18>, mb<19>, mb<20>, mb<21>, mb<22>, mb<23>, mb<24>, mb<25>};
-  const char *names[] = {"v_add_f32", "v_fmac_f32", "v_fma_f32 (vop3,neg)", "v_med3_f32", "v_max_f32", "v_fmac_f32_dpp", "v_mov_b32_dpp", "v_cndmask_b32 vcc", "v_sub_f32", "v_cmp_gt_f32 ->sgpr", "v_cmp_gt_f32 ->vcc", "v_addc carry sgpr", "v_addc carry vcc", "v_add_u32", "v_pk_add_u16", "v_pk_max_i16", "v_permlane16_swap", "v_alignbit_b32", "v_lshl_or_b32", "v_lshrrev_b32", "v_xor_b32", "v_bfi_b32", "v_min_f32", "v_max3_f32", "v_mul_f32", "v_cndmask sgpr"};
-  for (int v = 0; v < 26; ++v) {
+  K ks[] = {mb<0>, mb<1>, mb<2>, mb<3>, mb<4>, mb<5>, mb<6>, mb<7>, mb<8>, mb<9>, mb<10>, mb<11>, mb<12>, mb<13>, mb<14>, mb<15>, mb<16>, mb<17>, mb<18>, mb<19>, mb<20>, mb<21>, mb<22>, mb<23>, mb<24>, mb<25>, mb<26>, mb<27>};
+  const char *names[] = {"v_add_f32", "v_fmac_f32", "v_fma_f32 (vop3,neg)", "v_med3_f32", "v_max_f32", "v_fmac_f32_dpp", "v_mov_b32_dpp", "v_cndmask_b32 vcc", "v_sub_f32", "v_cmp_gt_f32 ->sgpr", "v_cmp_gt_f32 ->vcc", "v_addc carry sgpr", "v_addc carry vcc", "v_add_u32", "v_pk_add_u16", "v_pk_max_i16", "v_permlane16_swap", "v_alignbit_b32", "v_lshl_or_b32", "v_lshrrev_b32", "v_xor_b32", "v_bfi_b32", "v_min_f32", "v_max3_f32", "v_mul_f32", "v_cndmask sgpr", "v_readlane_b32", "v_writelane_b32"};
+  for (int v = 0; v < 28; ++v) {
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0);
       hipLaunchKernelGGL(ks[v], dim3(blocks), dim3(threads), 0, 0, out, iters);
