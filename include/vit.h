@@ -81,7 +81,9 @@ typedef struct {
   int32_t llr_type;      /* VIT_LLR_F32 (float), VIT_LLR_I8 (int8) or VIT_LLR_HARD */
   int32_t terminated;    /* 1: the stream carries k-1 tail stages (default 1)    */
   int32_t v1;            /* left overlap; -1 = floor(v/2) (default -1)           */
-  int32_t check_finite;  /* reserved, must be 0                                  */
+  int32_t check_finite;  /* 1: scan FP32 LLRs first and return VIT_EINVAL if any is
+                          * NaN or infinite (the call then waits for the scan on
+                          * `stream`); 0 (default): LLRs must be finite, unchecked */
   int32_t reserved;
   void *stream;          /* hipStream_t to launch on; NULL = default stream      */
   /* Subframe traceback (Sec. IV-D).  0 (default): each block is traced back

@@ -23,13 +23,15 @@ __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Serve
            "VIT_TIE_LOWER_PRED"]
 
 
-def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, subframe_overlap=2, out=None,
-           stream=None):
+def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, subframe_overlap=2, check_finite=False,
+           out=None, stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
     values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
     subframe_words F > 0 splits each block's traceback into subframes of F
     survivor words with subframe_overlap words of inner overlap (see
-    vit_opts); 0 traces each block back once.  Returns (or fills) a uint8 device
+    vit_opts); 0 traces each block back once.  check_finite scans FP32 LLRs
+    first and raises VitError(VIT_EINVAL) on a NaN or infinity (the call then
+    waits for the scan).  Returns (or fills) a uint8 device
     tensor of ceil(n/8) packed bytes.  Asynchronous on `stream` (default:
     torch's current stream)."""
     import torch
@@ -56,6 +58,7 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, su
     opts.llr_type = llr_type
     opts.terminated = 1 if terminated else 0
     opts.v1 = -1 if v1 is None else int(v1)
+    opts.check_finite = 1 if check_finite else 0
     opts.subframe_words = int(subframe_words)
     opts.subframe_overlap = int(subframe_overlap)
     if stream is None:

@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "vit_check.h"
 #include "vit_internal.h"
 
 namespace {
@@ -159,7 +160,7 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   if (!out_bits) return fail(VIT_EINVAL, "out_bits is NULL");
   if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8 && o.llr_type != VIT_LLR_HARD)
     return fail(VIT_EINVAL, "unknown llr_type %d", o.llr_type);
-  if (o.check_finite != 0) return fail(VIT_EUNSUPPORTED, "check_finite is not implemented");
+  if (o.check_finite != 0 && o.check_finite != 1) return fail(VIT_EINVAL, "check_finite = %d (0 or 1)", o.check_finite);
   if (o.subframe_words < 0) return fail(VIT_EINVAL, "subframe_words = %d must be >= 0", o.subframe_words);
   if (o.subframe_words > 0 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
     return fail(VIT_EINVAL, "subframe_overlap = %d outside [0, 2^24]", o.subframe_overlap);
@@ -203,6 +204,12 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
     if ((words + o.subframe_words - 1) / o.subframe_words > 64)
       return fail(VIT_EUNSUPPORTED, "%lld survivor words per block in subframes of %d: more than 64 subframes",
                   (long long)words, o.subframe_words);
+  }
+  if (o.check_finite && o.llr_type == VIT_LLR_F32) {
+    int nonfinite = 0;
+    const hipError_t ce = vit::check_finite_f32((const float *)llr, g.N * code->beta, (hipStream_t)o.stream, &nonfinite);
+    if (ce != hipSuccess) return fail_hip(ce, "finiteness pre-pass");
+    if (nonfinite) return fail(VIT_EINVAL, "an LLR is NaN or infinite");
   }
   int unsupported = 0;
   const char *why = "";

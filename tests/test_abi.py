@@ -91,6 +91,9 @@ def test_invalid_arguments(vit):
     o = vit.vit_opts_default()
     o.terminated = 2
     _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
+    o = vit.vit_opts_default()
+    o.check_finite = 2
+    _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
     for sub, ov in ((-1, 2), (1, -1), (2, (1 << 24) + 1)):
         o = vit.vit_opts_default()
         o.subframe_words, o.subframe_overlap = sub, ov
@@ -112,9 +115,6 @@ def test_unsupported_arguments(vit):
     c = _code(vit)
     U = vit.VIT_EUNSUPPORTED
     _expect(vit, U, vit.vit_decode, c, FAKE, 100, 12, 4, 0, FAKE)      # L not a multiple of 8
-    o = vit.vit_opts_default()
-    o.check_finite = 1
-    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
     o = vit.vit_opts_default()
     o.llr_type = vit.VIT_LLR_I8
     # int8 metrics must stay exact in fp32: a block of 2^16 stages is refused

@@ -255,3 +255,34 @@ def test_ber_gap_ml_reference_is_ml(dev, ebn0):
     diff = int(np.sum(ref[: m - 64] != got[: m - 64]))
     print(f"Eb/N0 {ebn0}: {diff} bits differ from full-frame ML")
     assert diff <= (64 if ebn0 < 3.0 else 0)
+
+
+# ----------------------------------------------------------------------------- finiteness pre-pass
+
+def test_check_finite(dev):
+    # vit_opts.check_finite: finite input decodes exactly as without the check;
+    # a NaN or an infinity anywhere (vector and scalar paths of the scan,
+    # aligned and unaligned buffers) is refused with VIT_EINVAL
+    torch, vit = dev
+    k, gens = CODES["k7r12"]
+    code = vit.make_code(k, gens)
+    n = 5000
+    llr = _awgn(k, gens, n, 2.0, seed=77)
+    N2 = llr.size
+    for off in (0, 1):
+        buf = torch.zeros(N2 + 1, dtype=torch.float32, device="cuda")
+        t = buf[off:off + N2]
+        t.copy_(torch.from_numpy(llr))
+        plain = vit.decode(code, t, n, 256, 35).cpu().numpy()
+        checked = vit.decode(code, t, n, 256, 35, check_finite=True).cpu().numpy()
+        np.testing.assert_array_equal(checked, plain)
+        for bad, pos in ((float("nan"), 0), (float("inf"), N2 - 1), (float("-inf"), N2 // 2 + 3)):
+            t.copy_(torch.from_numpy(llr))
+            t[pos] = bad
+            print(f"[gpu] check_finite off={off} value={bad} at {pos}", flush=True)
+            with pytest.raises(vit.VitError) as ei:
+                vit.decode(code, t, n, 256, 35, check_finite=True)
+            assert ei.value.status == vit.VIT_EINVAL
+    q = vit.quantize(torch.from_numpy(llr).cuda(), 4.0)
+    np.testing.assert_array_equal(vit.decode(code, q, n, 256, 35, check_finite=True).cpu().numpy(),
+                                  vit.decode(code, q, n, 256, 35).cpu().numpy())
