@@ -145,6 +145,11 @@ def cpu_baseline(code_np, llr, n, L, v):
 BATCH_CODES = ("k7r12", "k7r13", "k9r12")
 
 
+def default_overlap(k):
+    """The library's default overlap of the batch and serving paths."""
+    return 5 * k if k <= 7 else 8 * (k - 1)
+
+
 def batched_workload(nframes, seed=0):
     """Batched configuration: terminated frames, lengths uniform in [40, 6144],
     code uniform over K=7 r1/2, K=7 r1/3, K=9 r1/2, Eb/N0 uniform in [1, 5] dB."""
@@ -460,22 +465,27 @@ def precision_sweep(vit, torch, log2n=24):
     LLRs (quantised on the GPU with the per-Eb/N0 scale: a noiseless symbol
     maps to 8), BER of each, the Eb/N0 each needs for BER 1e-4 (log-linear
     interpolation) and their difference, and both paths' stream throughput at
-    3 dB.  Block shapes: L=512, v=35 for K=7; L=256, v=45 for K=9."""
+    3 dB.  Block shapes: L=512, v=35 for K=7; L=256, v=64 for K=9 (the library's
+    default overlaps).  The ML reference is the blocked decoder with v1 = v2 =
+    128."""
     import numpy as np
     import synth
     n = 1 << log2n
     grid = list(range(7))
     res = {}
     out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
-    for name, (L, v) in (("k7r12", (512, 35)), ("k7r13", (512, 35)), ("k9r12", (256, 45))):
+    for name, (L, v) in (("k7r12", (512, 35)), ("k7r13", (512, 35)), ("k9r12", (256, default_overlap(9)))):
         k, gens = synth.CODES[name]
         code = vit.make_code(k, gens)
-        rows = {"fp32": [], "int8": []}
+        rows = {"fp32": [], "int8": [], "ml": []}
         mbps = {}
         for e in grid:
             bits, llr = synth.make_stream(name, n, float(e), seed=1 + e)
             d = torch.from_numpy(llr).cuda()
             q = vit.quantize(d, 8.0 * synth.noise_sigma(float(e), len(gens)) ** 2 / 2.0)
+            # the ML reference: FP32, blocks with v1 = v2 = 128 (far beyond convergence)
+            vit.decode(code, d, n, 512, 256, v1=128, out=out)
+            rows["ml"].append(int(np.sum(synth.unpack_bits(out.cpu().numpy(), n) != bits)))
             for tag, x in (("fp32", d), ("int8", q)):
                 vit.decode(code, x, n, L, v, out=out)
                 got = synth.unpack_bits(out.cpu().numpy(), n)
@@ -493,12 +503,32 @@ def precision_sweep(vit, torch, log2n=24):
                     return grid[i] + (np.log(1e-4) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
             return None
 
-        af, aq = at_1e4(rows["fp32"]), at_1e4(rows["int8"])
+        af, aq, am = at_1e4(rows["fp32"]), at_1e4(rows["int8"]), at_1e4(rows["ml"])
+
+        def ml_gap(errs):
+            """Per grid point: the Eb/N0 shift at which the ML curve reaches this BER."""
+            mb = [max(x, 0.5) / n for x in rows["ml"]]
+            out_g = []
+            for e, x in zip(grid, errs):
+                b = max(x, 0.5) / n
+                at = None
+                for i in range(len(grid) - 1):
+                    if mb[i] >= b > mb[i + 1]:
+                        y0, y1 = np.log(mb[i]), np.log(mb[i + 1])
+                        at = grid[i] + (np.log(b) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
+                out_g.append(None if at is None or x == 0 else round(float(e - at), 4))
+            return out_g
+
         res[name] = {"L": L, "v": v, "ebn0_db": grid,
                      "ber_fp32": [x / n for x in rows["fp32"]], "ber_int8": [x / n for x in rows["int8"]],
+                     "ber_ml": [x / n for x in rows["ml"]],
                      "ebn0_at_1e-4_fp32": None if af is None else round(float(af), 4),
                      "ebn0_at_1e-4_int8": None if aq is None else round(float(aq), 4),
+                     "ebn0_at_1e-4_ml": None if am is None else round(float(am), 4),
                      "int8_loss_db": None if af is None or aq is None else round(float(aq - af), 4),
+                     "int8_loss_vs_ml_db": None if am is None or aq is None else round(float(aq - am), 4),
+                     "gap_to_ml_per_point_fp32": ml_gap(rows["fp32"]),
+                     "gap_to_ml_per_point_int8": ml_gap(rows["int8"]),
                      "mbps_at_3db": mbps}
     return {"workload": f"2^{log2n}-bit terminated streams, BPSK/AWGN, seed 1 + Eb/N0; int8 scale 8 sigma^2 / 2",
             "codes": res}
@@ -622,7 +652,8 @@ def main():
         batched["vs_stream_fp32"] = round(batched["mbps"] / head["mbps"], 3)
     serving = None
     if not args.no_serving:
-        tunes = batched["tuning_tuples"] if batched else [(256, 5 * synth.CODES[c][0], -1, 1) for c in BATCH_CODES]
+        tunes = batched["tuning_tuples"] if batched else [(256, default_overlap(synth.CODES[c][0]), -1, 1)
+                                                          for c in BATCH_CODES]
         serving = bench_serving(vit, torch, args, tunes)
     if batched:
         batched.pop("tuning_tuples", None)

@@ -206,7 +206,7 @@ int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_fr
  * buffer of llr_count elements of llr_type (VIT_LLR_F32, VIT_LLR_I8 or
  * VIT_LLR_HARD); out: device buffer of out_bytes
  * bytes (frames' output ranges must not overlap); tune: one vit_tuning per
- * code, or NULL for the plan's autotuned shapes (default L = 256, v = 5k,
+ * code, or NULL for the plan's autotuned shapes (default L = 256, v = 5k for k <= 7 and 8(k-1) above,
  * 1 wave per workgroup when not tuned); workspace: device memory of at least
  * vit_batch_workspace_size bytes, 256-byte aligned, not used by concurrent
  * calls.  Asynchronous on `stream`; the host staging of the previous use of
@@ -220,7 +220,8 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
                      void *stream);
 
 /* Autotune: for each code, time the batch's frames of that code with every
- * candidate shape (L in {64, 128, 256, 512, 1024}, v = 5k, v1 = floor(v/2),
+ * candidate shape (L in {64, 128, 256, 512, 1024}, v = 5k for k <= 7 and 8(k-1)
+ * above, v1 = floor(v/2),
  * 1 or 2 waves per workgroup) and keep the fastest in the plan, keyed by
  * (code, llr_type, frame-length bucket).  chosen (may be NULL) receives one
  * vit_tuning per code.  Same buffers and errors as vit_decode_batch; the
@@ -294,7 +295,8 @@ typedef struct {
 int vit_server_workspace_size(const vit_server_config *cfg, size_t *bytes);
 
 /* Create a server for ncodes (1..8) codes with one block shape per code
- * (tune = NULL: L = 256, v = 5k, v1 = floor(v/2), 1 wave per workgroup).
+ * (tune = NULL: L = 256, v = 5k for k <= 7 and 8(k-1) above, v1 = floor(v/2),
+ * 1 wave per workgroup).
  * The arena, workspace and host region stay owned by the caller and must stay
  * valid until vit_server_destroy returns.  Errors: VIT_EINVAL for bad codes,
  * shapes, sizes or buffers (not device/pinned memory, misaligned, too small);

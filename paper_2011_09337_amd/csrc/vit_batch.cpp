@@ -20,6 +20,7 @@
 
 #include "vit.h"
 #include "vit_internal.h"
+#include "vit_shapes.h"
 
 struct vit_plan {
   void *staging[2] = {nullptr, nullptr};
@@ -74,7 +75,7 @@ bool same_tuning(const vit_tuning &a, const vit_tuning &b) {
 vit_tuning default_tuning(const vit_code &c) {
   vit_tuning t;
   t.L = 256;
-  t.v = 5 * c.k;
+  t.v = vit::default_overlap(c.k);
   t.v1 = -1;
   t.waves_per_block = 1;
   return t;

@@ -28,6 +28,7 @@
 
 #include "vit.h"
 #include "vit_internal.h"
+#include "vit_shapes.h"
 #include "vit_server_core.h"
 
 namespace {
@@ -371,7 +372,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
       shape[c] = tune[c];
     } else {
       shape[c].L = 256;
-      shape[c].v = 5 * codes[c].k;
+      shape[c].v = vit::default_overlap(codes[c].k);
       shape[c].v1 = -1;
       shape[c].waves_per_block = 1;
     }

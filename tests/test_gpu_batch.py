@@ -158,8 +158,10 @@ def test_autotune_then_decode(dev):
     b = vit.Batch()
     chosen = b.autotune(codes, frames, t_llr, out)
     print("autotuned:", chosen[:3])
-    for t in chosen[:3]:
+    for c, t in enumerate(chosen[:3]):
+        k = CODES[c][0]
         assert t[0] in (64, 128, 256, 512, 1024) and t[3] in (1, 2)
+        assert t[1] == (5 * k if k <= 7 else 8 * (k - 1))  # the library's default overlap
     out.zero_()
     b.decode(codes, frames, t_llr, out)  # tune=None: the plan's choices
     torch.cuda.synchronize()
