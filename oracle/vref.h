@@ -16,7 +16,7 @@
  *   traceback .......... Sec. II-B, Algorithm 2 (backward)
  *   overlapping frames . Sec. III (frames of f bits, left overlap v1, right v2)
  *
- * Conventions (the paper leaves these open; each choice is listed in the design doc):
+ * Conventions (the paper leaves these open; these are the readings taken):
  *   - gen[b] is a k-bit generator; its bit k-1 taps the current input in_t
  *     and bit 0 taps in_{t-k+1} (eq. 1 multiplies in_t by g_{k-1}).
  *   - output bit b of a stage is produced by gen[b], in the order listed.
