@@ -554,7 +554,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the decoder has no multi-GPU path "
-              f"in this build.", file=sys.stderr)
+              f"in this library.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
