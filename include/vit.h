@@ -35,7 +35,8 @@
  *   - L = 0 selects full-frame decoding: one block holding every stage.
  *
  * Pointers to LLRs and to decoded bits are DEVICE memory owned by the caller;
- * the library allocates no device memory on the decode path.
+ * the library allocates no device memory on the decode path (except one flag
+ * word per device for the optional finiteness pre-pass, on its first use).
  *
  * Return values: VIT_OK (0) or a negative status.  Argument errors are found
  * on the host before any device work (and need no GPU).  vit_last_error()
