@@ -75,10 +75,20 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(fn), 64 * wpb, lds);
   if (err != hipSuccess) return err;
   if (occ < 1) occ = 1;
-  int64_t grid = (int64_t)occ * t_dev.num_cu;
+  // Grid: one workgroup per wpb blocks (the hardware dispatcher refills a CU
+  // as soon as a workgroup ends), except for long blocks or low occupancy,
+  // where persistent waves that loop over blocks are faster.  Measured on
+  // 2^24-bit streams: one block per wave is 5-15% faster for K=7 up to
+  // L = 896 and K=9 up to L = 448; persistent waves are 5-16% faster from
+  // about 1000 stages per block (K=5..7, L = 1024, 2048) and at 4 or fewer
+  // workgroups per CU (K=9, L = 512).
   const int64_t need = (a.nblocks + wpb - 1) / wpb;
-  if (grid >= need) grid = need;
-  else grid = grid / 8 * 8;
+  int64_t grid = need;
+  if (a.max_block_stages >= 1000 || occ <= 4) {
+    grid = (int64_t)occ * t_dev.num_cu;
+    if (grid >= need) grid = need;
+    else grid = grid / 8 * 8;
+  }
   if (grid < 1) grid = 1;
   if (lds > 65536) {
     err = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
