@@ -34,6 +34,13 @@ struct vit_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t copy_node = nullptr;
+  // per code: its kernel node, launch shape, arguments and current grid
+  hipGraphNode_t knode[vit::kMaxCodes] = {};
+  vit::BatchLaunch bl[vit::kMaxCodes] = {};
+  vit::BatchArgs kargs[vit::kMaxCodes] = {};
+  int kwords[vit::kMaxCodes] = {};
+  bool persistent[vit::kMaxCodes] = {};
+  unsigned kgrid[vit::kMaxCodes] = {};
   struct Key {
     const void *llr = nullptr;
     void *out = nullptr;
@@ -360,6 +367,10 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     if (llr_type != VIT_LLR_F32 && ((int64_t)shape[c].L + shape[c].v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
       return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
 
+  int ncu = 256;
+  he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (he != hipSuccess) return vit::api_fail_hip(he, "hipDeviceGetAttribute");
+
   // graph: reuse while buffers, codes and shapes are unchanged
   vit_plan::Key key;
   key.llr = llr;
@@ -375,9 +386,20 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     key.tune[c] = shape[c];
     if (same) same = same_code(plan->key.codes[c], codes[c]) && same_tuning(plan->key.tune[c], shape[c]);
   }
+  // Grid per code: one workgroup per waves_per_block items (the dispatcher
+  // refills a CU as a workgroup ends), or, for blocks of 1000 stages or more
+  // or at 4 or fewer workgroups per CU, the occupancy-sized grid of
+  // persistent waves (the same rule as the stream kernel's launch).
+  auto grid_for = [&](int c) -> unsigned {
+    if (plan->persistent[c]) return plan->bl[c].grid;
+    const int64_t cnt = header[kMaxCodes + c];
+    const int64_t wpb = shape[c].waves_per_block;
+    const int64_t g = (cnt + wpb - 1) / wpb;
+    return (unsigned)(g < 1 ? 1 : g);
+  };
   if (!same) {
     // launch shapes (LDS sized for the longest block a shape can produce)
-    vit::BatchLaunch bl[kMaxCodes];
+    vit::BatchLaunch *bl = plan->bl;
     for (int c = 0; c < ncodes; ++c) {
       int unsupported = 0;
       const char *why = "";
@@ -386,6 +408,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
                                   &why);
       if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
       if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
+      plan->persistent[c] = (int64_t)shape[c].L + shape[c].v >= 1000 || bl[c].grid <= 4u * (unsigned)ncu;
     }
     drop_graph(plan);
     he = hipGraphCreate(&plan->graph, 0);
@@ -404,19 +427,20 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     hipGraphNode_t prev = plan->copy_node;
     for (int oi = 0; oi < ncodes; ++oi) {
       const int c = order[oi];
-      vit::BatchArgs args;
+      vit::BatchArgs &args = plan->kargs[c];
       args.llr = llr;
       args.out = out;
       args.header = (int32_t *)workspace;
       args.items = (const WorkItem *)((char *)workspace + kHeaderBytes);
       args.code_index = c;
       for (int b = 0; b < 4; ++b) args.gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0u;
-      int words = bl[c].lds_words_per_wave;
-      void *kargs[] = {&args, &words};
+      plan->kwords[c] = bl[c].lds_words_per_wave;
+      void *kargs[] = {&args, &plan->kwords[c]};
+      plan->kgrid[c] = grid_for(c);
       hipKernelNodeParams kp;
       memset(&kp, 0, sizeof(kp));
       kp.func = const_cast<void *>(bl[c].fn);
-      kp.gridDim = dim3(bl[c].grid);
+      kp.gridDim = dim3(plan->kgrid[c]);
       kp.blockDim = dim3(bl[c].block);
       kp.sharedMemBytes = (unsigned)bl[c].lds;
       kp.kernelParams = kargs;
@@ -424,6 +448,7 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
       hipGraphNode_t kn;
       he = hipGraphAddKernelNode(&kn, plan->graph, &prev, 1, &kp);
       if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddKernelNode");
+      plan->knode[c] = kn;
       prev = kn;
     }
     he = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
@@ -434,6 +459,23 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     he = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->copy_node, workspace, stg, need,
                                            hipMemcpyHostToDevice);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphExecMemcpyNodeSetParams1D");
+    // the item counts change from call to call: resize the dispatcher-refilled grids
+    for (int c = 0; c < ncodes; ++c) {
+      const unsigned g = grid_for(c);
+      if (g == plan->kgrid[c]) continue;
+      void *kargs[] = {&plan->kargs[c], &plan->kwords[c]};
+      hipKernelNodeParams kp;
+      memset(&kp, 0, sizeof(kp));
+      kp.func = const_cast<void *>(plan->bl[c].fn);
+      kp.gridDim = dim3(g);
+      kp.blockDim = dim3(plan->bl[c].block);
+      kp.sharedMemBytes = (unsigned)plan->bl[c].lds;
+      kp.kernelParams = kargs;
+      kp.extra = nullptr;
+      he = hipGraphExecKernelNodeSetParams(plan->exec, plan->knode[c], &kp);
+      if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphExecKernelNodeSetParams");
+      plan->kgrid[c] = g;
+    }
   }
   he = hipGraphLaunch(plan->exec, (hipStream_t)stream);
   if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphLaunch");
