@@ -3,12 +3,13 @@
 //
 // A batch is cut into blocks exactly as each frame would be on its own
 // (Sec. III of the paper, per frame).  Each block is one work item; items of
-// one code are sorted by cost (stages) so the persistent waves of that code's
-// kernel take the longest first.  Per call the host writes the header (item
+// one code are sorted by cost (stages) so that the kernel's waves take the
+// longest first.  Per call the host writes the header (item
 // counts and run offsets per code) and the items into pinned staging memory;
 // the graph copies them into the caller's device workspace and runs one kernel
 // node per code, in sequence.  While the buffers, codes and shapes stay the
-// same the graph is reused and only its copy node is updated.
+// same the graph is reused; only its copy node and the kernel grids (sized to
+// each code's item count) are updated.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -39,7 +40,6 @@ struct vit_plan {
   vit::BatchLaunch bl[vit::kMaxCodes] = {};
   vit::BatchArgs kargs[vit::kMaxCodes] = {};
   int kwords[vit::kMaxCodes] = {};
-  bool persistent[vit::kMaxCodes] = {};
   unsigned kgrid[vit::kMaxCodes] = {};
   struct Key {
     const void *llr = nullptr;
@@ -386,16 +386,9 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
     key.tune[c] = shape[c];
     if (same) same = same_code(plan->key.codes[c], codes[c]) && same_tuning(plan->key.tune[c], shape[c]);
   }
-  // Grid per code: one workgroup per waves_per_block items (the dispatcher
-  // refills a CU as a workgroup ends), or, for blocks of 1000 stages or more
-  // or at 4 or fewer workgroups per CU, the occupancy-sized grid of
-  // persistent waves (the same rule as the stream kernel's launch).
   auto grid_for = [&](int c) -> unsigned {
-    if (plan->persistent[c]) return plan->bl[c].grid;
-    const int64_t cnt = header[kMaxCodes + c];
-    const int64_t wpb = shape[c].waves_per_block;
-    const int64_t g = (cnt + wpb - 1) / wpb;
-    return (unsigned)(g < 1 ? 1 : g);
+    return vit::batch_grid(header[kMaxCodes + c], shape[c].waves_per_block, (int64_t)shape[c].L + shape[c].v,
+                           plan->bl[c].grid, ncu);
   };
   if (!same) {
     // launch shapes (LDS sized for the longest block a shape can produce)
@@ -408,7 +401,6 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
                                   &why);
       if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
       if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
-      plan->persistent[c] = (int64_t)shape[c].L + shape[c].v >= 1000 || bl[c].grid <= 4u * (unsigned)ncu;
     }
     drop_graph(plan);
     he = hipGraphCreate(&plan->graph, 0);

@@ -89,6 +89,7 @@ int check_memory(const void *p, size_t bytes, hipMemoryType want, const char *wh
 
 struct vit_server {
   int dev = 0;
+  int num_cu = 256;
   hipStream_t stream = nullptr;
   int llr_type = VIT_LLR_I8;
   int elem = 1;
@@ -200,9 +201,8 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     for (int b = 0; b < 4; ++b) a.gen[b] = b < s->codes[c].beta ? s->codes[c].gen[b] : 0u;
     int words = s->bl[c].lds_words_per_wave;
     void *kargs[] = {&a, &words};
-    const unsigned wpb = s->bl[c].block / 64;
-    unsigned grid = (unsigned)((it.count[c] + wpb - 1) / wpb);
-    if (grid > s->bl[c].grid) grid = s->bl[c].grid;
+    const unsigned grid = vit::batch_grid(it.count[c], (int)(s->bl[c].block / 64),
+                                          (int64_t)s->shape[c].L + s->shape[c].v, s->bl[c].grid, s->num_cu);
     e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
     if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
   }
@@ -410,6 +410,8 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
   };
   hipError_t e = hipGetDevice(&s->dev);
   if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipGetDevice"));
+  e = hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, s->dev);
+  if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipDeviceGetAttribute"));
   void *hd = nullptr;
   e = hipHostGetDevicePointer(&hd, cfg->host, 0);
   if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostGetDevicePointer"));
