@@ -393,6 +393,8 @@ def bench_serving(vit, torch, args, tunes):
                 "mean_items_per_iteration": round(st["items_launched"] / max(1, st["iterations"]), 1),
                 "peak_frames_on_device": st["peak_frames_on_device"],
                 "peak_arena_MiB": round(st["peak_arena_bytes"] / 2 ** 20, 2)})
+            print(f"serving: load {load:g} done ({st['completed']} frames, p99 {points[-1]['p99_ms']} ms)",
+                  file=sys.stderr, flush=True)
     finally:
         srv.close()
     return {
