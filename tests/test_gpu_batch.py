@@ -177,3 +177,27 @@ def test_batch_single_and_tiny_frames(dev):
     got = run_batch(dev, b, frames, llr, out_bytes, None, TUNE)
     check_frames(got, frames, llr, TUNE)
     b.close()
+
+
+def test_long_blocks_beside_short_ones(dev):
+    # blocks of 1000 stages or more (K=7 at L=1024; K=9 at L=2048, where few
+    # workgroups fit on a CU) run a grid of persistent waves that stride over
+    # their items; the short-block code beside them runs one workgroup per
+    # item pair; the plan is reused with changing item counts
+    torch, vit = dev
+    tune = [(1024, 35, -1, 1), (128, 21, -1, 2), (2048, 64, 20, 1), (64, 25, -1, 1), (32, 20, -1, 4)]
+    b = vit.Batch()
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    rng = np.random.default_rng(21)
+    cap_llr, cap_out = 4_000_000, 400_000
+    t_llr = torch.zeros(cap_llr, dtype=torch.float32, device="cuda")
+    out = torch.zeros(cap_out, dtype=torch.uint8, device="cuda")
+    for it, (nf, nmax) in enumerate([(40, 20000), (7, 6000), (90, 9000)]):
+        frames, llr, out_bytes, _ = make_batch(rng, nf, [0, 1, 2], 1, nmax)
+        assert llr.size <= cap_llr and out_bytes <= cap_out
+        t_llr[:llr.size].copy_(torch.from_numpy(llr))
+        print(f"[gpu] long blocks, call {it}: {len(frames)} frames up to {nmax} bits", flush=True)
+        b.decode(codes, frames, t_llr, out, tune=tune)
+        torch.cuda.synchronize()
+        check_frames(out.cpu().numpy(), frames, llr, tune)
+    b.close()
