@@ -201,6 +201,55 @@ DEFINE_FULL(vref_decode_full_f32, window_f32, float, float)
 DEFINE_FULL(vref_decode_full_f64, window_f64, double, double)
 DEFINE_FULL(vref_decode_full_i8, window_i8, int64_t, int8_t)
 
+/* 16-bit modulo metrics (see vref.h).  wrap16 reduces an integer modulo 2^16
+ * into [-2^15, 2^15); a is "greater" than b when the wrapped difference a - b
+ * is positive.  The forward and backward procedures are those of the window
+ * above (Algorithms 1 and 2, ties to the lower predecessor, argmax with the
+ * lowest index on ties), with these two operations in place of + and >. */
+static int16_t wrap16(int64_t x) {
+  const int64_t r = x & 0xffff;
+  return (int16_t)(r >= 0x8000 ? r - 0x10000 : r);
+}
+static int gt16(int16_t a, int16_t b) { return wrap16((int64_t)a - (int64_t)b) > 0; }
+
+int vref_decode_full_i16mod(const vref_code *code, const int8_t *llr, int64_t n,
+                            int32_t terminated, uint8_t *out, int16_t *final_metric) {
+  if (!code_ok(code) || n <= 0 || !llr || !out) return -1;
+  trellis tr;
+  build_trellis(code, &tr);
+  const int S = tr.S, kk = code->k, beta = code->beta;
+  const int words = (S + 63) / 64;
+  const int64_t N = n + (terminated ? kk - 1 : 0);
+  int16_t pm[VREF_MAX_S], nm[VREF_MAX_S];
+  uint64_t *dec = (uint64_t *)calloc((size_t)N * (size_t)words, sizeof(uint64_t));
+  if (!dec) return -2;
+  for (int j = 0; j < S; ++j) pm[j] = j == 0 ? 0 : wrap16(-(1 << 14));
+  for (int64_t t = 0; t < N; ++t) {
+    const int8_t *l = llr + t * beta;
+    uint64_t *dt = dec + t * words;
+    for (int j = 0; j < S; ++j) {
+      const int16_t m0 = wrap16((int64_t)pm[tr.pred[j][0]] + bm_i8(l, beta, tr.aout[j][0]));
+      const int16_t m1 = wrap16((int64_t)pm[tr.pred[j][1]] + bm_i8(l, beta, tr.aout[j][1]));
+      const int d = gt16(m1, m0);
+      nm[j] = d ? m1 : m0;
+      if (d) dt[j >> 6] |= 1ull << (j & 63);
+    }
+    memcpy(pm, nm, sizeof(int16_t) * (size_t)S);
+  }
+  int jstar = 0;
+  if (!terminated)
+    for (int j = 1; j < S; ++j)
+      if (gt16(pm[j], pm[jstar])) jstar = j;
+  if (final_metric) *final_metric = pm[jstar];
+  for (int64_t t = N - 1; t >= 0; --t) {
+    if (t < n) out[t] = (uint8_t)(jstar >> (kk - 2));
+    const int d = (int)((dec[t * words + (jstar >> 6)] >> (jstar & 63)) & 1u);
+    jstar = ((jstar << 1) & (S - 1)) | d;
+  }
+  free(dec);
+  return 0;
+}
+
 /* Sec. III: frames of L output bits, each decoded from its own window that
  * adds v1 stages of history on the left and v2 stages on the right, clipped
  * to the stream.  A window that starts at stage 0 knows the encoder state;

@@ -58,6 +58,16 @@ int vref_decode_full_f64(const vref_code *code, const double *llr, int64_t n,
 /* Integer LLRs (e.g. int8-quantised), exact int64 path metrics. */
 int vref_decode_full_i8(const vref_code *code, const int8_t *llr, int64_t n,
                         int32_t terminated, uint8_t *out, int64_t *final_metric);
+/* The same integer decode with 16-bit path metrics kept modulo 2^16, as a
+ * fixed-width integer datapath would hold them (the paper does not discuss
+ * metric overflow): every sum wraps, and two metrics are compared by the sign
+ * of their wrapped difference.  States other than 0 start at -2^14 instead of
+ * minus infinity.  Its decisions equal the exact ones while any two compared
+ * metrics differ by less than 2^15; it exists to check that reading against
+ * vref_decode_full_i8.  final_metric receives the traced path's metric modulo
+ * 2^16 (as a signed 16-bit value). */
+int vref_decode_full_i16mod(const vref_code *code, const int8_t *llr, int64_t n,
+                            int32_t terminated, uint8_t *out, int16_t *final_metric);
 
 /* Blocked decoding with overlap (Sec. III): the n output bits are split into
  * cores of L bits; block b covers trellis stages

@@ -58,10 +58,12 @@ def _declare(L):
     L.vref_decode_blocked_split_i8.argtypes = [C.POINTER(VrefCode), _P, i64, i32, i64, i64, i64, i64, i64, i64,
                                                _P, i32]
     L.vref_depuncture_i8.argtypes = [_P, i64, _P, i32, i32, i64, _P]
+    L.vref_decode_full_i16mod.argtypes = [C.POINTER(VrefCode), _P, i64, i32, _P, _P]
     for fn in (L.vref_encode, L.vref_decode_full_f32, L.vref_decode_full_f64, L.vref_decode_full_i8,
                L.vref_decode_blocked_f32, L.vref_decode_blocked_f64, L.vref_decode_blocked_i8,
                L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window, L.vref_depuncture_f32,
-               L.vref_depuncture_i8, L.vref_decode_blocked_split_f32, L.vref_decode_blocked_split_i8):
+               L.vref_depuncture_i8, L.vref_decode_blocked_split_f32, L.vref_decode_blocked_split_i8,
+               L.vref_decode_full_i16mod):
         fn.restype = C.c_int
 
 
@@ -118,6 +120,19 @@ def decode_full(code, llr, n, terminated=True, want_metric=False):
         raise TypeError(llr.dtype)
     _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), _ptr(out), C.byref(met)), fn.__name__)
     return (out, met.value) if want_metric else out
+
+
+def decode_full_i16mod(code, llr, n, terminated=True):
+    """Full-frame decode of int8 LLRs with 16-bit path metrics modulo 2^16
+    (compared by the sign of the wrapped difference).  Returns (bits, the
+    traced path's metric as a signed 16-bit value)."""
+    llr = np.ascontiguousarray(llr, dtype=np.int8)
+    assert llr.size == n_stages(code, n, terminated) * code.beta, "llr size"
+    out = np.zeros(n, dtype=np.uint8)
+    met = C.c_int16()
+    _check(lib().vref_decode_full_i16mod(C.byref(code), _ptr(llr), n, int(bool(terminated)), _ptr(out),
+                                         C.byref(met)), "vref_decode_full_i16mod")
+    return out, met.value
 
 
 def split_overlap(v, v1=None):

@@ -296,6 +296,54 @@ def test_quantize_round_half_even_and_saturation():
     assert vref.quantize_i8(np.array([-200.0, 200.0], np.float32), 1.0).min() == -127
 
 
+def _adversarial_i8(code, nst, rng):
+    """Saturated int8 LLRs over nst stages, in runs of random kind and length:
+    random signs at +-127, a noiseless codeword at +-127 (the best path pulls
+    away from the rest as fast as it can), all zeros (every compare a tie),
+    and constant +127 or -127."""
+    beta = code.beta
+    parts, left = [], nst
+    while left > 0:
+        m = min(left, int(rng.integers(64, 4097)))
+        kind = int(rng.integers(0, 5))
+        if kind == 0:
+            x = np.where(rng.random(m * beta) < 0.5, -127, 127)
+        elif kind == 1:
+            coded = vref.encode(code, rng.integers(0, 2, m, dtype=np.uint8), terminated=False)
+            x = np.where(coded != 0, -127, 127)
+        elif kind == 2:
+            x = np.zeros(m * beta)
+        else:
+            x = np.full(m * beta, 127 if kind == 3 else -127)
+        parts.append(x.astype(np.int8))
+        left -= m
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("k,gens,log2_stages", [(7, (0o171, 0o133), 20), (7, (0o133, 0o171, 0o165), 18),
+                                                (9, (0o561, 0o753), 18)])
+@pytest.mark.parametrize("terminated", [True, False])
+def test_int16_modulo_metrics_decide_like_exact_integers(k, gens, log2_stages, terminated):
+    # 16-bit metrics modulo 2^16, compared by the sign of the wrapped
+    # difference, take the exact integer decisions as long as compared metrics
+    # differ by less than 2^15: path metrics of one stage differ by at most
+    # (k-1)*2*127*beta (any state reaches any other in k-1 steps), 9144 /
+    # 13716 / 12192 here, plus the 2^14 start offset of unreachable states in
+    # the first k-1 stages.  Over 2^18-2^20 saturated stages the metrics wrap
+    # hundreds of times or more, so a plain compare of the stored values would
+    # fail.
+    code = _code(k, gens)
+    rng = np.random.default_rng(1000 + k + 10 * len(gens) + int(terminated))
+    nst = 1 << log2_stages
+    n = nst - (k - 1 if terminated else 0)
+    q = _adversarial_i8(code, nst, rng)
+    exact, m_exact = vref.decode_full(code, q, n, terminated, want_metric=True)
+    mod, m_mod = vref.decode_full_i16mod(code, q, n, terminated)
+    assert abs(m_exact) > (1 << 16) * 500, "the metrics must wrap many times"
+    np.testing.assert_array_equal(mod, exact)
+    assert (m_mod - m_exact) % (1 << 16) == 0
+
+
 # --------------------------------------------------------------------------- subframe traceback, Sec. IV-D
 
 def _chains(cs, e, k, G, F, W):
