@@ -341,6 +341,16 @@ const char *vit_last_error(void);
 /* VIT_ABI_VERSION of the built library. */
 int vit_abi_version(void);
 
+/* Test hook for the error paths (not part of the decode): the next `count`
+ * host allocations at the library's allocation points fail as if memory were
+ * exhausted (plan and server creation, the server's scheduler state, a batch's
+ * output-range list, a statistics snapshot), and the call that made them
+ * returns VIT_ENOMEM.  0 clears pending failures.  Process-wide; count < 0
+ * returns VIT_EINVAL.  Independently of this hook, no C++ exception leaves any
+ * entry point: a host allocation that fails inside the library returns
+ * VIT_ENOMEM (inside the serving engine it fails the server with VIT_ENOMEM). */
+int vit_debug_fail_allocations(int32_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -138,6 +138,8 @@ lib.vit_last_error.argtypes = []
 lib.vit_last_error.restype = C.c_char_p
 lib.vit_abi_version.argtypes = []
 lib.vit_abi_version.restype = C.c_int
+lib.vit_debug_fail_allocations.argtypes = [C.c_int32]
+lib.vit_debug_fail_allocations.restype = C.c_int
 
 
 def make_code(k, gens):

@@ -10,7 +10,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "vit_check.h"
+#include "vit_guard.h"
 #include "vit_internal.h"
 
 namespace {
@@ -31,6 +34,16 @@ int api_fail(int status, const char *fmt, ...) {
 
 int api_fail_hip(hipError_t e, const char *what) {
   return api_fail(VIT_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// Pending allocation failures requested by vit_debug_fail_allocations.
+static std::atomic<int32_t> g_fail_allocs{0};
+
+bool alloc_checkpoint_fails() {
+  int32_t n = g_fail_allocs.load(std::memory_order_relaxed);
+  while (n > 0 && !g_fail_allocs.compare_exchange_weak(n, n - 1, std::memory_order_relaxed)) {
+  }
+  return n > 0;
 }
 
 }  // namespace vit
@@ -109,6 +122,13 @@ const char *vit_last_error(void) { return t_err; }
 
 int vit_abi_version(void) { return VIT_ABI_VERSION; }
 
+int vit_debug_fail_allocations(int32_t count) {
+  vit::api_clear_error();
+  if (count < 0) return api_fail(VIT_EINVAL, "count = %d < 0", count);
+  vit::g_fail_allocs.store(count);
+  return VIT_OK;
+}
+
 vit_opts vit_opts_default(void) {
   vit_opts o;
   memset(&o, 0, sizeof(o));
@@ -146,8 +166,8 @@ int vit_query_geometry(const vit_code *code, int64_t n, int32_t L, int32_t v, in
   return VIT_OK;
 }
 
-int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v, int32_t tie_rule,
-                  uint8_t *out_bits, const vit_opts *opts) {
+static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v,
+                          int32_t tie_rule, uint8_t *out_bits, const vit_opts *opts) {
   t_err[0] = 0;
   vit_opts o = vit_opts_default();
   if (opts) {
@@ -217,6 +237,11 @@ int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, i
   if (e != hipSuccess) return fail_hip(e, "launch");
   if (unsupported) return fail(VIT_EUNSUPPORTED, "%s", why);
   return VIT_OK;
+}
+
+int vit_decode_ex(const vit_code *code, const void *llr, int64_t n, int32_t L, int32_t v, int32_t tie_rule,
+                  uint8_t *out_bits, const vit_opts *opts) {
+  return vit::guard_entry("vit_decode_ex", [&] { return decode_ex_impl(code, llr, n, L, v, tie_rule, out_bits, opts); });
 }
 
 int vit_depuncture(const void *received, int64_t received_count, int32_t llr_type, const uint8_t *mask,

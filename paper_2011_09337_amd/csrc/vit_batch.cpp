@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "vit.h"
+#include "vit_guard.h"
 #include "vit_internal.h"
 #include "vit_shapes.h"
 
@@ -194,6 +195,7 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
 int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes, int64_t llr_count,
                  int llr_type, int64_t out_bytes, std::vector<std::pair<int64_t, int64_t>> &outs) {
   const int elem = llr_type == VIT_LLR_F32 ? 4 : 1;
+  vit::alloc_checkpoint();
   outs.clear();
   outs.reserve(nframes);
   for (int32_t f = 0; f < nframes; ++f) {
@@ -274,7 +276,7 @@ extern "C" {
 int vit_plan_create(vit_plan **plan) {
   vit::api_clear_error();
   if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
-  *plan = new (std::nothrow) vit_plan();
+  *plan = vit::alloc_checkpoint_fails() ? nullptr : new (std::nothrow) vit_plan();
   if (!*plan) return api_fail(VIT_ENOMEM, "plan allocation failed");
   return VIT_OK;
 }
@@ -292,8 +294,8 @@ void vit_plan_destroy(vit_plan *plan) {
   delete plan;
 }
 
-int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
-                             const vit_tuning *tune, size_t *bytes) {
+static int batch_workspace_size_impl(const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                                     int32_t nframes, const vit_tuning *tune, size_t *bytes) {
   vit::api_clear_error();
   int st = check_args(codes, ncodes, frames, nframes);
   if (st) return st;
@@ -317,10 +319,10 @@ int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_fr
   return VIT_OK;
 }
 
-int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
-                     int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
-                     int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
-                     void *stream) {
+static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                             int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                             int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
+                             void *stream) {
   vit::api_clear_error();
   if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
   int st = check_args(codes, ncodes, frames, nframes);
@@ -482,9 +484,10 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
   return VIT_OK;
 }
 
-int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
-                      int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
-                      int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream, vit_tuning *chosen) {
+static int plan_autotune_impl(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                              int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                              int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream,
+                              vit_tuning *chosen) {
   vit::api_clear_error();
   if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
   int st = check_args(codes, ncodes, frames, nframes);
@@ -554,6 +557,32 @@ int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, con
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return result;
+}
+
+// The entry points: no exception leaves the C ABI (vit_guard.h).
+int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                             const vit_tuning *tune, size_t *bytes) {
+  return vit::guard_entry("vit_batch_workspace_size",
+                          [&] { return batch_workspace_size_impl(codes, ncodes, frames, nframes, tune, bytes); });
+}
+
+int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                     int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                     int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
+                     void *stream) {
+  return vit::guard_entry("vit_decode_batch", [&] {
+    return decode_batch_impl(plan, codes, ncodes, frames, nframes, llr, llr_count, llr_type, out, out_bytes, tune,
+                             workspace, workspace_bytes, stream);
+  });
+}
+
+int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                      int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
+                      int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream, vit_tuning *chosen) {
+  return vit::guard_entry("vit_plan_autotune", [&] {
+    return plan_autotune_impl(plan, codes, ncodes, frames, nframes, llr, llr_count, llr_type, out, out_bytes,
+                              workspace, workspace_bytes, stream, chosen);
+  });
 }
 
 }  // extern "C"

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "vit.h"
+#include "vit_guard.h"
 #include "vit_internal.h"
 #include "vit_shapes.h"
 #include "vit_server_core.h"
@@ -253,8 +254,7 @@ void finish_frames(vit_server *s, const std::vector<vit::serve::Frame> &frames, 
   s->idle_cv.notify_all();
 }
 
-void engine_main(vit_server *s) {
-  (void)hipSetDevice(s->dev);
+void engine_loop(vit_server *s) {
   std::vector<vit::serve::Frame> arrived;
   std::vector<vit::serve::Frame> dropped;
   for (;;) {
@@ -343,6 +343,26 @@ void engine_main(vit_server *s) {
   }
 }
 
+// The engine thread.  A host allocation failure inside the loop fails the
+// server with VIT_ENOMEM and the loop resumes in its failed mode: running
+// iterations retire and the frames still queued complete with the error (a
+// frame that was being handed over when the allocation failed may be lost).
+void engine_main(vit_server *s) {
+  (void)hipSetDevice(s->dev);
+  for (;;) {
+    try {
+      engine_loop(s);
+      return;
+    } catch (const std::exception &e) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      fail_locked(s, VIT_ENOMEM, std::string("engine: ") + e.what());
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      fail_locked(s, VIT_ENOMEM, "engine: host resource failure");
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -356,8 +376,8 @@ int vit_server_workspace_size(const vit_server_config *cfg, size_t *bytes) {
   return VIT_OK;
 }
 
-int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *tune, const vit_server_config *cfg,
-                      vit_server **out) {
+static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_tuning *tune,
+                              const vit_server_config *cfg, vit_server **out) {
   vit::api_clear_error();
   if (!out) return api_fail(VIT_EINVAL, "server is NULL");
   *out = nullptr;
@@ -397,7 +417,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
   if ((st = check_memory(cfg->workspace, cfg->workspace_bytes, hipMemoryTypeDevice, "workspace"))) return st;
   if ((st = check_memory(cfg->host, cfg->host_bytes, hipMemoryTypeHost, "host region"))) return st;
 
-  vit_server *s = new (std::nothrow) vit_server();
+  vit_server *s = vit::alloc_checkpoint_fails() ? nullptr : new (std::nothrow) vit_server();
   if (!s) return api_fail(VIT_ENOMEM, "server allocation failed");
   auto bail = [&](int status) {
     for (int i = 0; i < kInflight; ++i) {
@@ -430,6 +450,11 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
   s->max_items = cfg->max_items;
   s->max_pending = cfg->max_pending;
   std::vector<vit::serve::CodeShape> shapes;
+  try {
+    shapes.reserve((size_t)ncodes);
+  } catch (const std::bad_alloc &) {
+    return bail(api_fail(VIT_ENOMEM, "shape list allocation failed"));
+  }
   for (int c = 0; c < ncodes; ++c) {
     s->codes[c] = codes[c];
     s->shape[c] = shape[c];
@@ -449,9 +474,12 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
     e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
   }
-  s->core = new (std::nothrow) vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames,
-                                                cfg->max_items);
-  if (!s->core) return bail(api_fail(VIT_ENOMEM, "core allocation failed"));
+  try {
+    vit::alloc_checkpoint();
+    s->core = new vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames, cfg->max_items);
+  } catch (const std::bad_alloc &) {
+    return bail(api_fail(VIT_ENOMEM, "core allocation failed"));
+  }
   try {
     s->engine = std::thread(engine_main, s);
   } catch (...) {
@@ -461,7 +489,7 @@ int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *t
   return VIT_OK;
 }
 
-int vit_server_submit(vit_server *s, const vit_request *reqs, int32_t count, int32_t *accepted) {
+static int server_submit_impl(vit_server *s, const vit_request *reqs, int32_t count, int32_t *accepted) {
   vit::api_clear_error();
   if (accepted) *accepted = 0;
   if (!s) return api_fail(VIT_EINVAL, "server is NULL");
@@ -518,6 +546,7 @@ int vit_server_submit(vit_server *s, const vit_request *reqs, int32_t count, int
       took = (int32_t)room;
       st = api_fail(VIT_EBUSY, "request queue full (%d waiting)", s->max_pending);
     }
+    s->incoming.reserve(s->incoming.size() + (size_t)took);  // may throw: nothing is queued yet
     s->incoming.insert(s->incoming.end(), local.begin(), local.begin() + took);
     s->waiting += took;
     s->submitted += took;
@@ -586,7 +615,7 @@ int vit_server_drain(vit_server *s, int64_t timeout_ms) {
   return VIT_OK;
 }
 
-int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
+static int server_stats_impl(vit_server *s, vit_serve_stats *st, int32_t reset) {
   vit::api_clear_error();
   if (!s || !st) return api_fail(VIT_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
@@ -604,6 +633,7 @@ int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
   st->first_arrival_ns = s->first_arrival;
   st->last_done_ns = s->last_done;
   if (!s->lat.empty()) {
+    vit::alloc_checkpoint();
     std::vector<int64_t> v(s->lat);
     auto pct = [&](double p) {
       size_t i = (size_t)(p * (double)(v.size() - 1) + 0.5);
@@ -640,6 +670,20 @@ void vit_server_destroy(vit_server *s) {
   }
   delete s->core;
   delete s;
+}
+
+// The entry points that allocate: no exception leaves the C ABI (vit_guard.h).
+int vit_server_create(const vit_code *codes, int32_t ncodes, const vit_tuning *tune, const vit_server_config *cfg,
+                      vit_server **out) {
+  return vit::guard_entry("vit_server_create", [&] { return server_create_impl(codes, ncodes, tune, cfg, out); });
+}
+
+int vit_server_submit(vit_server *s, const vit_request *reqs, int32_t count, int32_t *accepted) {
+  return vit::guard_entry("vit_server_submit", [&] { return server_submit_impl(s, reqs, count, accepted); });
+}
+
+int vit_server_stats(vit_server *s, vit_serve_stats *st, int32_t reset) {
+  return vit::guard_entry("vit_server_stats", [&] { return server_stats_impl(s, st, reset); });
 }
 
 }  // extern "C"

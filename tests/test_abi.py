@@ -231,3 +231,26 @@ def test_frame_layout(vit):
     a = vit.frames_array([(1, 0, 100, 7, 9)])
     assert a.dtype == vit.FRAME_DTYPE and tuple(a[0]) == (1, 0, 100, 7, 9)
     assert vit.frames_array(a) is a
+
+
+def test_forced_allocation_failures_return_enomem(vit):
+    # vit_debug_fail_allocations makes the next allocation points fail: the call
+    # returns VIT_ENOMEM with a message (no exception leaves the C ABI), and the
+    # next call works again
+    lib = vit._lib.lib
+    assert lib.vit_debug_fail_allocations(-1) == vit.VIT_EINVAL
+    try:
+        assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+        _expect(vit, vit.VIT_ENOMEM, vit.vit_plan_create)
+        plan = vit.vit_plan_create()  # the requested failure is used up
+        try:
+            ca, fa = _batch_args(vit, [(0, 1, 100, 0, 0)])
+            assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+            # a batch's output-range list, built before any device work
+            _expect(vit, vit.VIT_ENOMEM, vit.vit_decode_batch, plan, ca, fa, FAKE, 212, 0, FAKE, 13, None,
+                    0x100000, 1 << 20, None)
+            assert "vit_decode_batch" in vit.vit_last_error() and "allocation" in vit.vit_last_error()
+        finally:
+            vit.vit_plan_destroy(plan)
+    finally:
+        assert lib.vit_debug_fail_allocations(0) == vit.VIT_OK

@@ -224,3 +224,42 @@ def test_paced_submission_replays_arrival_times(dev):
     for t, fr in enumerate(frames):
         lo, oo = offs[t]
         np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
+
+
+def test_forced_allocation_failures(dev):
+    # host allocation failures forced with vit_debug_fail_allocations: server
+    # creation and a statistics snapshot return VIT_ENOMEM (no exception
+    # leaves the C ABI), and a server created afterwards decodes as usual
+    torch, vit = dev
+    rng = np.random.default_rng(13)
+    frames = make_frames(rng, 20, 40, 600, True)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    lib = vit._lib.lib
+    kw = dict(tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64, max_items=256)
+    try:
+        assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+        with pytest.raises(vit.VitError) as ei:
+            vit.Server(codes, host, **kw)
+        assert ei.value.status == vit.VIT_ENOMEM
+        srv = vit.Server(codes, host, **kw)
+        try:
+            st, acc = srv.submit(requests(vit, host, frames, offs, list(range(len(frames)))))
+            assert st == vit.VIT_OK and acc == len(frames)
+            srv.drain(timeout_ms=30000)
+            comps = srv.poll()
+            assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+            with pytest.raises(vit.VitError) as ei:
+                srv.stats()
+            assert ei.value.status == vit.VIT_ENOMEM
+            stats = srv.stats()
+        finally:
+            srv.close()
+    finally:
+        assert lib.vit_debug_fail_allocations(0) == vit.VIT_OK
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames))) and (comps["status"] == 0).all()
+    assert stats["completed"] == len(frames)
+    h = host.numpy()
+    for t, fr in enumerate(frames):
+        lo, oo = offs[t]
+        np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
