@@ -220,6 +220,26 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
                      int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
                      void *stream);
 
+/* One autotuned shape as a plan keeps it: the code, the LLR type and the
+ * frame-length bucket it applies to (bucket b: the mean length of the batch's
+ * frames of that code lies in [2^b, 2^(b+1)); 0 below 2). */
+typedef struct {
+  vit_code code;
+  int32_t llr_type;
+  int32_t length_bucket;
+  vit_tuning tuning;
+} vit_tuning_entry;
+
+/* The plan's autotuned shapes, so that a caller can keep them (in a file,
+ * per GPU model) and hand them to another plan instead of tuning again.
+ * get: copies up to `max` entries (entries may be NULL when max = 0);
+ * *count receives how many the plan holds.  set: adds or replaces entries
+ * with the same (code, llr_type, length_bucket); every entry is validated
+ * (code, tuning, llr_type, bucket in [0, 40]) before any is taken, and the
+ * first bad one is reported with VIT_EINVAL. */
+int vit_plan_get_tuning(const vit_plan *plan, vit_tuning_entry *entries, int32_t max, int32_t *count);
+int vit_plan_set_tuning(vit_plan *plan, const vit_tuning_entry *entries, int32_t count);
+
 /* Autotune: for each code, time the batch's frames of that code with every
  * candidate shape (L in {64, 128, 256, 512, 1024}, v = 5k for k <= 7 and 8(k-1)
  * above, v1 = floor(v/2),

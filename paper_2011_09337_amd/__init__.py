@@ -7,7 +7,8 @@ PyTorch provides device memory and streams.
 """
 from . import _lib
 from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
-                   vit_plan_autotune, vit_plan_create, vit_plan_destroy)
+                   vit_plan_autotune, vit_plan_create, vit_plan_destroy, vit_plan_get_tuning, vit_plan_set_tuning,
+                   vit_tuning_entry)
 from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
                    vit_server_workspace_size)
@@ -17,7 +18,7 @@ from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LL
 
 __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
-           "vit_plan_destroy", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
+           "vit_plan_destroy", "vit_plan_get_tuning", "vit_plan_set_tuning", "vit_tuning_entry", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
            "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8", "VIT_LLR_HARD",
            "VIT_TIE_LOWER_PRED"]
@@ -149,6 +150,49 @@ class Batch:
         vit_decode_batch(self.plan, codes_arr, frames_arr, llr.data_ptr(), llr.numel(), llr_type, out.data_ptr(),
                          out.numel(), tune_arr, ws, ws_bytes, stream.cuda_stream)
         return out
+
+    def tuning(self):
+        """The plan's autotuned shapes: dicts with the code (k, gens), llr_type,
+        length_bucket and the shape (L, v, v1, waves_per_block)."""
+        return [{"k": e.code.k, "gens": [int(g) for g in e.code.gen[:e.code.beta]], "llr_type": e.llr_type,
+                 "length_bucket": e.length_bucket, "L": e.L, "v": e.v, "v1": e.v1,
+                 "waves_per_block": e.waves_per_block} for e in vit_plan_get_tuning(self.plan)]
+
+    def set_tuning(self, entries):
+        """Add autotuned shapes (dicts as returned by `tuning`) to the plan."""
+        arr = []
+        for d in entries:
+            e = vit_tuning_entry()
+            e.code = make_code(d["k"], d["gens"])
+            e.llr_type, e.length_bucket = int(d["llr_type"]), int(d["length_bucket"])
+            e.L, e.v, e.v1, e.waves_per_block = int(d["L"]), int(d["v"]), int(d["v1"]), int(d["waves_per_block"])
+            arr.append(e)
+        vit_plan_set_tuning(self.plan, arr)
+
+    @staticmethod
+    def _device_name(device_name):
+        if device_name is not None:
+            return device_name
+        import torch
+        return torch.cuda.get_device_name()
+
+    def save_tuning(self, path, device_name=None):
+        """Write the plan's autotuned shapes to a JSON file, keyed by the GPU
+        model (torch's device name unless `device_name` is given)."""
+        import json
+        with open(path, "w") as f:
+            json.dump({"device": self._device_name(device_name), "entries": self.tuning()}, f, indent=1)
+
+    def load_tuning(self, path, device_name=None):
+        """Take the shapes of a file written by `save_tuning` if it was tuned on
+        the same GPU model; returns how many were taken (0 for another GPU)."""
+        import json
+        with open(path) as f:
+            data = json.load(f)
+        if data.get("device") != self._device_name(device_name):
+            return 0
+        self.set_tuning(data["entries"])
+        return len(data["entries"])
 
     def autotune(self, codes, frames, llr, out, stream=None):
         import torch

@@ -36,6 +36,11 @@ class vit_opts(C.Structure):
                 ("stream", C.c_void_p), ("subframe_words", C.c_int32), ("subframe_overlap", C.c_int32)]
 
 
+class vit_tuning_entry(C.Structure):
+    _fields_ = [("code", vit_code), ("llr_type", C.c_int32), ("length_bucket", C.c_int32),
+                ("L", C.c_int32), ("v", C.c_int32), ("v1", C.c_int32), ("waves_per_block", C.c_int32)]
+
+
 class vit_geometry(C.Structure):
     _fields_ = [("n_stages", C.c_int64), ("n_blocks", C.c_int64), ("v1", C.c_int64), ("v2", C.c_int64),
                 ("stages_total", C.c_int64), ("max_block_stages", C.c_int64),
@@ -140,6 +145,10 @@ lib.vit_abi_version.argtypes = []
 lib.vit_abi_version.restype = C.c_int
 lib.vit_debug_fail_allocations.argtypes = [C.c_int32]
 lib.vit_debug_fail_allocations.restype = C.c_int
+lib.vit_plan_get_tuning.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+lib.vit_plan_get_tuning.restype = C.c_int
+lib.vit_plan_set_tuning.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+lib.vit_plan_set_tuning.restype = C.c_int
 
 
 def make_code(k, gens):
@@ -237,6 +246,20 @@ def vit_plan_create():
 
 def vit_plan_destroy(plan):
     lib.vit_plan_destroy(plan)
+
+
+def vit_plan_get_tuning(plan):
+    """The plan's autotuned shapes as a vit_tuning_entry array."""
+    n = C.c_int32()
+    _check(lib.vit_plan_get_tuning(plan, None, 0, C.byref(n)))
+    arr = (vit_tuning_entry * max(1, n.value))()
+    _check(lib.vit_plan_get_tuning(plan, arr, n.value, C.byref(n)))
+    return arr[:n.value]
+
+
+def vit_plan_set_tuning(plan, entries):
+    arr = (vit_tuning_entry * max(1, len(entries)))(*entries)
+    return _check(lib.vit_plan_set_tuning(plan, arr, len(entries)))
 
 
 def vit_batch_workspace_size(codes_arr, frames_arr, tune_arr=None):

@@ -53,7 +53,8 @@ struct vit_plan {
     vit_tuning tune[vit::kMaxCodes];
   } key;
 
-  std::map<std::string, vit_tuning> tuned;
+  // autotuned shapes by (code, LLR type, frame-length bucket)
+  std::map<std::string, vit_tuning_entry> tuned;
 
   // host scratch reused across calls (large per-call vectors would be mmap'd
   // and page-faulted afresh every call)
@@ -236,7 +237,7 @@ int resolve_shapes(vit_plan *plan, const vit_code *codes, int32_t ncodes, const 
         }
       const int bucket = frame_bucket(cnt ? sum / cnt : 0);
       auto it = plan->tuned.find(tune_key(codes[c], llr_type, bucket));
-      shape[c] = it != plan->tuned.end() ? it->second : default_tuning(codes[c]);
+      shape[c] = it != plan->tuned.end() ? it->second.tuning : default_tuning(codes[c]);
     }
     const int st = check_tuning(shape[c]);
     if (st) return st;
@@ -550,7 +551,12 @@ static int plan_autotune_impl(vit_plan *plan, const vit_code *codes, int32_t nco
       }
     }
     if (result == VIT_OK) {
-      plan->tuned[tune_key(codes[c], llr_type, frame_bucket(sum / (int64_t)sub.size()))] = best;
+      const int bucket = frame_bucket(sum / (int64_t)sub.size());
+      vit_tuning_entry &ent = plan->tuned[tune_key(codes[c], llr_type, bucket)];
+      ent.code = codes[c];
+      ent.llr_type = llr_type;
+      ent.length_bucket = bucket;
+      ent.tuning = best;
       if (chosen) chosen[c] = best;
     }
   }
@@ -583,6 +589,48 @@ int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, con
     return plan_autotune_impl(plan, codes, ncodes, frames, nframes, llr, llr_count, llr_type, out, out_bytes,
                               workspace, workspace_bytes, stream, chosen);
   });
+}
+
+int vit_plan_get_tuning(const vit_plan *plan, vit_tuning_entry *entries, int32_t max, int32_t *count) {
+  vit::api_clear_error();
+  if (!plan || !count || max < 0 || (max > 0 && !entries)) return api_fail(VIT_EINVAL, "bad arguments");
+  *count = (int32_t)plan->tuned.size();
+  int32_t i = 0;
+  for (const auto &kv : plan->tuned) {
+    if (i >= max) break;
+    entries[i++] = kv.second;
+  }
+  return VIT_OK;
+}
+
+static int plan_set_tuning_impl(vit_plan *plan, const vit_tuning_entry *entries, int32_t count) {
+  vit::api_clear_error();
+  if (!plan || count < 0 || (count > 0 && !entries)) return api_fail(VIT_EINVAL, "bad arguments");
+  for (int32_t i = 0; i < count; ++i) {  // all entries are checked before any is taken
+    const vit_tuning_entry &e = entries[i];
+    int st = vit::api_check_code(&e.code);
+    if (!st) st = check_tuning(e.tuning);
+    if (st) {
+      char why[256];
+      snprintf(why, sizeof(why), "%s", vit_last_error());  // api_fail rewrites that buffer
+      return api_fail(st, "entry %d: %s", i, why);
+    }
+    if (e.llr_type != VIT_LLR_F32 && e.llr_type != VIT_LLR_I8 && e.llr_type != VIT_LLR_HARD)
+      return api_fail(VIT_EINVAL, "entry %d: unknown llr_type %d", i, e.llr_type);
+    if (e.length_bucket < 0 || e.length_bucket > 40)
+      return api_fail(VIT_EINVAL, "entry %d: length_bucket %d outside [0, 40]", i, e.length_bucket);
+  }
+  vit::alloc_checkpoint();
+  for (int32_t i = 0; i < count; ++i) {
+    vit_tuning_entry e = entries[i];
+    for (int b = e.code.beta; b < 4; ++b) e.code.gen[b] = 0;
+    plan->tuned[tune_key(e.code, e.llr_type, e.length_bucket)] = e;
+  }
+  return VIT_OK;
+}
+
+int vit_plan_set_tuning(vit_plan *plan, const vit_tuning_entry *entries, int32_t count) {
+  return vit::guard_entry("vit_plan_set_tuning", [&] { return plan_set_tuning_impl(plan, entries, count); });
 }
 
 }  // extern "C"

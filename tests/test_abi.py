@@ -254,3 +254,37 @@ def test_forced_allocation_failures_return_enomem(vit):
             vit.vit_plan_destroy(plan)
     finally:
         assert lib.vit_debug_fail_allocations(0) == vit.VIT_OK
+
+
+def test_tuning_export_import(vit, tmp_path):
+    # a plan's autotuned shapes go out and come back in (vit_plan_get_tuning /
+    # vit_plan_set_tuning), and through a JSON file keyed by the GPU model
+    import ctypes
+    assert ctypes.sizeof(vit.vit_tuning_entry) == 48
+    b = vit.Batch()
+    b2 = vit.Batch()
+    try:
+        assert b.tuning() == []
+        ents = [dict(k=7, gens=[0o171, 0o133], llr_type=vit.VIT_LLR_I8, length_bucket=10, L=512, v=35, v1=-1,
+                     waves_per_block=1),
+                dict(k=9, gens=[0o561, 0o753], llr_type=vit.VIT_LLR_I8, length_bucket=11, L=256, v=64, v1=20,
+                     waves_per_block=2)]
+        b.set_tuning(ents)
+        assert sorted(b.tuning(), key=lambda d: d["k"]) == ents
+        b.set_tuning([dict(ents[0], L=256)])  # same key: replaced
+        got = sorted(b.tuning(), key=lambda d: d["k"])
+        assert len(got) == 2 and got[0]["L"] == 256
+        for bad in (dict(ents[1], L=12), dict(ents[1], llr_type=9), dict(ents[1], length_bucket=41),
+                    dict(ents[1], k=10), dict(ents[1], waves_per_block=0)):
+            with pytest.raises(vit.VitError) as ei:
+                b.set_tuning([dict(ents[0], length_bucket=3), bad])  # the good first entry is not taken either
+            assert ei.value.status == vit.VIT_EINVAL and "entry 1" in vit.vit_last_error(), bad
+            assert len(b.tuning()) == 2
+        path = str(tmp_path / "tuning.json")
+        b.save_tuning(path, device_name="gpu-a")
+        assert b2.load_tuning(path, device_name="gpu-b") == 0 and b2.tuning() == []
+        assert b2.load_tuning(path, device_name="gpu-a") == 2
+        assert sorted(b2.tuning(), key=lambda d: d["k"]) == got
+    finally:
+        b.close()
+        b2.close()

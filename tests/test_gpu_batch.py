@@ -201,3 +201,24 @@ def test_long_blocks_beside_short_ones(dev):
         torch.cuda.synchronize()
         check_frames(out.cpu().numpy(), frames, llr, tune)
     b.close()
+
+
+def test_imported_tuning_is_used(dev):
+    # a shape handed to the plan (vit_plan_set_tuning) for the batch's code,
+    # LLR type and frame-length bucket is the one decode(tune=None) uses
+    torch, vit = dev
+    rng = np.random.default_rng(31)
+    frames, llr, out_bytes, _ = make_batch(rng, 50, [0], 300, 700, ebn0=(1.0, 2.0))
+    mean = sum(f[2] for f in frames) // len(frames)
+    shape = (128, 21, 5, 2)
+    b = vit.Batch()
+    k, gens = CODES[0]
+    b.set_tuning([dict(k=k, gens=list(gens), llr_type=vit.VIT_LLR_F32, length_bucket=mean.bit_length() - 1,
+                       L=shape[0], v=shape[1], v1=shape[2], waves_per_block=shape[3])])
+    got = run_batch(dev, b, frames, llr, out_bytes, None, None)
+    check_frames(got, frames, llr, [shape])
+    # the default shape decodes these noisy frames differently somewhere
+    default = (256, 35, -1, 1)
+    assert any(not np.array_equal(got[fr[4]:fr[4] + (fr[2] + 7) // 8], oracle_frame(fr, llr, default))
+               for fr in frames)
+    b.close()
