@@ -60,7 +60,8 @@ enum {
   VIT_EUNSUPPORTED = -2,  /* valid, but outside what the GPU kernel supports   */
   VIT_ENOMEM = -3,        /* host allocation failed                            */
   VIT_EDEVICE = -4,       /* a HIP runtime call or kernel launch failed        */
-  VIT_EBUSY = -5
+  VIT_EBUSY = -5,
+  VIT_ETIMEDOUT = -6      /* a serving request waited longer than max_wait_ms  */
 };
 
 enum { VIT_TIE_LOWER_PRED = 0 };
@@ -275,7 +276,9 @@ typedef struct {
   int32_t max_frames;        /* frames admitted to the device at once (slots), >= 1  */
   int32_t max_items;         /* blocks per iteration, >= 1                           */
   int32_t max_pending;       /* queued requests beyond which submit says VIT_EBUSY   */
-  int32_t reserved;
+  int32_t max_wait_ms;       /* a request still queued (not admitted) this long after
+                                its arrival completes with VIT_ETIMEDOUT, undecoded;
+                                checked in queue order; 0 = no limit                 */
   void *arena;               /* device, 256-aligned: admitted frames' LLRs + output  */
   size_t arena_bytes;        /* the memory budget that admission respects            */
   void *workspace;           /* device, 256-aligned, vit_server_workspace_size bytes */
@@ -299,7 +302,8 @@ typedef struct {
 
 typedef struct {
   uint64_t tag;
-  int32_t status;            /* VIT_OK, or the device error that stopped the server  */
+  int32_t status;            /* VIT_OK, VIT_ETIMEDOUT, or the device error that
+                                stopped the server                                   */
   int32_t reserved;
   int64_t arrival_ns, done_ns;
 } vit_completion;

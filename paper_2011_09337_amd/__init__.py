@@ -9,14 +9,14 @@ from . import _lib
 from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy, vit_plan_get_tuning, vit_plan_set_tuning,
                    vit_tuning_entry)
-from ._lib import (VIT_EBUSY, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
+from ._lib import (VIT_EBUSY, VIT_ETIMEDOUT, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
                    vit_server_workspace_size)
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_HARD, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry, vit_depuncture)
 
-__all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "codes_array", "frames_array", "tunings_array",
+__all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "VIT_ETIMEDOUT", "codes_array", "frames_array", "tunings_array",
            "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "vit_plan_get_tuning", "vit_plan_set_tuning", "vit_tuning_entry", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
@@ -226,7 +226,7 @@ class Server:
     output bytes (requests address it by byte offset, see `requests`)."""
 
     def __init__(self, codes, host, *, tune=None, llr_type=VIT_LLR_I8, arena_bytes=64 << 20, max_frames=4096,
-                 max_items=65536, max_pending=1 << 20, device="cuda", stream=None):
+                 max_items=65536, max_pending=1 << 20, max_wait_ms=0, device="cuda", stream=None):
         import torch
 
         if not host.is_pinned() or host.dtype != torch.uint8:
@@ -239,6 +239,7 @@ class Server:
         cfg.max_frames = max_frames
         cfg.max_items = max_items
         cfg.max_pending = max_pending
+        cfg.max_wait_ms = max_wait_ms
         ws_bytes = vit_server_workspace_size(cfg)
         self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
         self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=device)

@@ -17,13 +17,15 @@ VIT_EUNSUPPORTED = -2
 VIT_ENOMEM = -3
 VIT_EDEVICE = -4
 VIT_EBUSY = -5
+VIT_ETIMEDOUT = -6
 VIT_TIE_LOWER_PRED = 0
 VIT_LLR_F32 = 0
 VIT_LLR_I8 = 1
 VIT_LLR_HARD = 2
 
 STATUS_NAMES = {VIT_OK: "VIT_OK", VIT_EINVAL: "VIT_EINVAL", VIT_EUNSUPPORTED: "VIT_EUNSUPPORTED",
-                VIT_ENOMEM: "VIT_ENOMEM", VIT_EDEVICE: "VIT_EDEVICE", VIT_EBUSY: "VIT_EBUSY"}
+                VIT_ENOMEM: "VIT_ENOMEM", VIT_EDEVICE: "VIT_EDEVICE", VIT_EBUSY: "VIT_EBUSY",
+                VIT_ETIMEDOUT: "VIT_ETIMEDOUT"}
 
 
 class vit_code(C.Structure):
@@ -58,7 +60,7 @@ class vit_tuning(C.Structure):
 
 class vit_server_config(C.Structure):
     _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("max_frames", C.c_int32),
-                ("max_items", C.c_int32), ("max_pending", C.c_int32), ("reserved", C.c_int32),
+                ("max_items", C.c_int32), ("max_pending", C.c_int32), ("max_wait_ms", C.c_int32),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("host", C.c_void_p), ("host_bytes", C.c_size_t),
                 ("stream", C.c_void_p)]

@@ -66,6 +66,7 @@ int check_config(const vit_server_config *cfg) {
   if (cfg->max_items < 1 || cfg->max_items > (1 << 24))
     return api_fail(VIT_EINVAL, "max_items = %d outside [1, 2^24]", cfg->max_items);
   if (cfg->max_pending < 1) return api_fail(VIT_EINVAL, "max_pending = %d must be >= 1", cfg->max_pending);
+  if (cfg->max_wait_ms < 0) return api_fail(VIT_EINVAL, "max_wait_ms = %d must be >= 0", cfg->max_wait_ms);
   return VIT_OK;
 }
 
@@ -106,6 +107,7 @@ struct vit_server {
   uint8_t *host_dev = nullptr;  // the same region as the device addresses it
   size_t host_bytes = 0;
   int32_t max_frames = 0, max_items = 0, max_pending = 0;
+  int64_t max_wait_ns = 0;  // queue timeout, 0 = none
 
   void *staging[kInflight] = {nullptr, nullptr};
   hipEvent_t ev[kInflight] = {nullptr, nullptr};
@@ -256,6 +258,7 @@ void finish_frames(vit_server *s, const std::vector<vit::serve::Frame> &frames, 
 
 void engine_loop(vit_server *s) {
   std::vector<vit::serve::Frame> arrived;
+  std::vector<vit::serve::Frame> expired;
   std::vector<vit::serve::Frame> dropped;
   for (;;) {
     bool stop, failed;
@@ -267,6 +270,13 @@ void engine_loop(vit_server *s) {
     }
     for (const auto &f : arrived) s->core->submit(f);
     arrived.clear();
+    if (s->max_wait_ns > 0 && !failed) {
+      // queue timeouts, before anything more is admitted
+      const int64_t now = mono_ns();
+      expired.clear();
+      s->core->expire_queued(now - s->max_wait_ns, [&](const vit::serve::Frame &f) { expired.push_back(f); });
+      if (!expired.empty()) finish_frames(s, expired, VIT_ETIMEDOUT, now, 0);
+    }
 
     // retire finished iterations, oldest first
     bool progressed = false;
@@ -449,6 +459,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   s->max_frames = cfg->max_frames;
   s->max_items = cfg->max_items;
   s->max_pending = cfg->max_pending;
+  s->max_wait_ns = (int64_t)cfg->max_wait_ms * 1000000;
   std::vector<vit::serve::CodeShape> shapes;
   try {
     shapes.reserve((size_t)ncodes);

@@ -245,6 +245,20 @@ class Core {
     active_.clear();
   }
 
+  // Queue timeouts: drop queued frames that arrived before cutoff_ns, taken
+  // from the front of the queue (the order of admission) while they are
+  // expired, reporting each to fn(frame).  Admitted frames always complete.
+  template <class Fn>
+  int64_t expire_queued(int64_t cutoff_ns, Fn fn) {
+    int64_t n = 0;
+    while (!pending_.empty() && pending_.front().arrival_ns < cutoff_ns) {
+      fn(pending_.front());
+      pending_.pop_front();
+      ++n;
+    }
+    return n;
+  }
+
   // The iteration has finished on the device: release its frames' arena.
   void retire(const Iteration &it) {
     for (const Frame &f : it.finishing) {

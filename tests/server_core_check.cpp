@@ -235,6 +235,45 @@ int main(int argc, char **argv) {
   }
   CHECK(!core.has_work() && inflight.empty() && core.arena_in_use() == 0, "work left at the end");
 
+  // queue timeouts: expire_queued drops expired frames from the front of the
+  // queue only (an early arrival behind a live frame waits for its turn)
+  {
+    Core q(shapes, elem, arena, max_frames, max_items);
+    const int64_t arrivals[5] = {5, 7, 20, 3, 30};
+    for (int j = 0; j < 5; ++j) {
+      Frame f;
+      f.tag = 1000 + (uint64_t)j;
+      f.code = 0;
+      f.terminated = 1;
+      f.n = 16;
+      f.N = 22;
+      f.llr_bytes = 44 * elem;
+      f.llr_src = 0;
+      f.out_dst = 0;
+      f.arrival_ns = arrivals[j];
+      CHECK(q.fits_ever(f), "timeout frame does not fit");
+      q.submit(f);
+    }
+    std::vector<uint64_t> gone;
+    auto note = [&](const Frame &f) { gone.push_back(f.tag); };
+    CHECK(q.expire_queued(10, note) == 2 && gone.size() == 2 && gone[0] == 1000 && gone[1] == 1001,
+          "expire at 10");
+    CHECK(q.pending() == 3, "pending after the first expiry");
+    CHECK(q.expire_queued(25, note) == 2 && gone[2] == 1002 && gone[3] == 1003, "expire at 25");
+    CHECK(q.pending() == 1 && q.expire_queued(30, note) == 0, "arrival 30 is not before 30");
+    Iteration it;
+    VectorSink sink;
+    CHECK(q.next_iteration(&it, sink) && it.admitted == 1, "the remaining frame is admitted");
+    CHECK(q.expire_queued(1000, note) == 0, "admitted frames never expire");
+    q.retire(it);
+    for (int rounds = 0; q.has_work() && rounds < 100; ++rounds) {  // blocks left for later iterations
+      Iteration more;
+      q.next_iteration(&more, sink);
+      q.retire(more);
+    }
+    CHECK(!q.has_work() && q.arena_in_use() == 0, "timeout core left work");
+  }
+
   // fail_all drops queued and admitted frames and frees their arena
   for (int j = 0; j < 20; ++j) {
     Frame f;

@@ -263,3 +263,40 @@ def test_forced_allocation_failures(dev):
     for t, fr in enumerate(frames):
         lo, oo = offs[t]
         np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
+
+
+def test_queue_timeout(dev):
+    # requests still queued max_wait_ms after their arrival complete with
+    # VIT_ETIMEDOUT and are not decoded (their output bytes stay as they
+    # were); the requests behind them decode as usual
+    torch, vit = dev
+    rng = np.random.default_rng(14)
+    frames = make_frames(rng, 30, 40, 600, True)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64,
+                     max_items=256, max_wait_ms=1000)
+    try:
+        reqs = requests(vit, host, frames, offs, list(range(len(frames))))
+        reqs["arrival_ns"][:10] = time.monotonic_ns() - 5_000_000_000  # at the front, already 5 s old
+        before = host.numpy().copy()
+        st, acc = srv.submit(reqs)
+        assert st == vit.VIT_OK and acc == len(frames)
+        srv.drain(timeout_ms=30000)
+        comps = srv.poll()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    by_tag = {int(c["tag"]): int(c["status"]) for c in comps}
+    assert sorted(by_tag) == list(range(len(frames)))
+    assert all(by_tag[t] == vit.VIT_ETIMEDOUT for t in range(10))
+    assert all(by_tag[t] == vit.VIT_OK for t in range(10, len(frames)))
+    assert stats["completed"] == len(frames) - 10 and stats["failed"] == 10
+    h = host.numpy()
+    for t, fr in enumerate(frames):
+        lo, oo = offs[t]
+        nb = (fr[2] + 7) // 8
+        if t < 10:
+            np.testing.assert_array_equal(h[oo:oo + nb], before[oo:oo + nb])
+        else:
+            np.testing.assert_array_equal(h[oo:oo + nb], expected_alone(torch, vit, fr, TUNE))

@@ -56,7 +56,7 @@ def test_workspace_size(vit):
 
 
 @pytest.mark.parametrize("kw", [dict(size=12), dict(llr_type=5), dict(max_frames=0), dict(max_items=0),
-                                dict(max_pending=0), dict(max_frames=1 << 21)])
+                                dict(max_pending=0), dict(max_frames=1 << 21), dict(max_wait_ms=-1)])
 def test_bad_config(vit, kw):
     with pytest.raises(vit.VitError) as ei:
         vit.vit_server_workspace_size(_cfg(vit, **kw))
