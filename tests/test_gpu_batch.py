@@ -222,3 +222,47 @@ def test_imported_tuning_is_used(dev):
     assert any(not np.array_equal(got[fr[4]:fr[4] + (fr[2] + 7) // 8], oracle_frame(fr, llr, default))
                for fr in frames)
     b.close()
+
+
+def test_batched_configuration_full_size_sampled(dev):
+    # the 8192-frame mixed-code configuration at its full size, prepared and
+    # launched as the benchmark does (int8 quantisation on the device, one
+    # graph launch, the shapes the autotuner picks there); every 8th frame is
+    # compared with the oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    import bench
+    torch, vit = dev
+    frames, llr, out_bytes, _, scales = bench.batched_workload(8192)
+    assert len(frames) == 8192
+    codes = [vit.make_code(*synth.CODES[c]) for c in bench.BATCH_CODES]
+    llr_d = torch.from_numpy(llr).cuda()
+    q_d = torch.empty(llr.size, dtype=torch.int8, device="cuda")
+    for (cid, term, n, lo, oo), sc in zip(frames, scales):
+        k, gens = synth.CODES[bench.BATCH_CODES[cid]]
+        cnt = (n + (k - 1 if term else 0)) * len(gens)
+        vit.vit_quantize_i8(llr_d.data_ptr() + 4 * lo, cnt, sc, q_d.data_ptr() + lo, None)
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    tunes = [(512, 35, -1, 1), (512, 35, -1, 1), (256, 64, -1, 2)]
+    b = vit.Batch()
+    print(f"[gpu] full-size batch: {len(frames)} frames, {sum(f[2] for f in frames)} bits", flush=True)
+    b.decode(codes, frames, q_d, out, tune=tunes)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    q = q_d.cpu().numpy()
+    b.close()
+
+    def want(fr):
+        cid, term, n, lo, oo = fr
+        k, gens = synth.CODES[bench.BATCH_CODES[cid]]
+        N = n + (k - 1 if term else 0)
+        L, v, _, _ = tunes[cid]
+        bits = vref.decode_blocked(vref.make_code(k, list(gens)), q[lo:lo + N * len(gens)], n, L, v // 2,
+                                   v - v // 2, bool(term))
+        return synth.pack_bits(bits)
+
+    sample = frames[::8]
+    with ThreadPoolExecutor(NCPU) as ex:
+        wants = list(ex.map(want, sample))
+    for fr, w in zip(sample, wants):
+        np.testing.assert_array_equal(got[fr[4]:fr[4] + w.size], w, err_msg=f"frame {fr}")
