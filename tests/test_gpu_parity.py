@@ -226,7 +226,7 @@ def test_synchronous_entry_point(dev):
 
 # ----------------------------------------------------------------------------- full size
 
-@pytest.mark.parametrize("L", [128, 1024])
+@pytest.mark.parametrize("L", [128, 512, 1024])
 def test_full_size_stream_k7(dev, L):
     # the 2^24-bit stream of the throughput workload, in the benchmark's launch
     # configuration; the oracle decodes it completely (all host cores)
