@@ -67,24 +67,28 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
     *why = "one block's survivor storage exceeds the per-workgroup LDS";
     return hipSuccess;
   }
-  // two waves per workgroup where their survivor storage fits (measured: about
-  // 8% faster than one, no gain from four)
-  const int wpb = (2 * lds_wave <= t_dev.max_lds) ? 2 : 1;
-  const size_t lds = (size_t)lds_wave * wpb;
+  // Grid: one block per wave, the hardware dispatcher refilling a CU as soon
+  // as a workgroup ends, except for long blocks or low occupancy, where
+  // persistent waves that loop over blocks are faster.  Measured on 2^24-bit
+  // streams: one block per wave is 5-15% faster for K=7 up to L = 896 and
+  // K=9 up to L = 448; persistent waves are 5-16% faster from about 1000
+  // stages per block (K=5..7, L = 1024, 2048) and at 4 or fewer two-wave
+  // workgroups per CU (K=9, L = 512).  Persistent waves run two per
+  // workgroup where their survivor storage fits (8-25% faster than one);
+  // one block per wave runs one wave per workgroup (K=7 r1/2 at L = 512:
+  // 64.0 against 62.2 Gb/s; -2% to +5% for the other codes and lengths).
+  int wpb = (2 * lds_wave <= t_dev.max_lds) ? 2 : 1;
   int occ = 0;
-  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(fn), 64 * wpb, lds);
+  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(fn), 64 * wpb,
+                                                     (size_t)lds_wave * wpb);
   if (err != hipSuccess) return err;
   if (occ < 1) occ = 1;
-  // Grid: one workgroup per wpb blocks (the hardware dispatcher refills a CU
-  // as soon as a workgroup ends), except for long blocks or low occupancy,
-  // where persistent waves that loop over blocks are faster.  Measured on
-  // 2^24-bit streams: one block per wave is 5-15% faster for K=7 up to
-  // L = 896 and K=9 up to L = 448; persistent waves are 5-16% faster from
-  // about 1000 stages per block (K=5..7, L = 1024, 2048) and at 4 or fewer
-  // workgroups per CU (K=9, L = 512).
+  const bool persistent = a.max_block_stages >= 1000 || occ <= 4;
+  if (!persistent) wpb = 1;
+  const size_t lds = (size_t)lds_wave * wpb;
   const int64_t need = (a.nblocks + wpb - 1) / wpb;
   int64_t grid = need;
-  if (a.max_block_stages >= 1000 || occ <= 4) {
+  if (persistent) {
     grid = (int64_t)occ * t_dev.num_cu;
     if (grid >= need) grid = need;
     else grid = grid / 8 * 8;
