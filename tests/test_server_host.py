@@ -96,3 +96,15 @@ def test_request_layouts(vit):
         assert vit.REQUEST_DTYPE.fields[name][1] == getattr(vit._lib.vit_request, name).offset
     for name, _ in vit._lib.vit_completion._fields_:
         assert vit.COMPLETION_DTYPE.fields[name][1] == getattr(vit._lib.vit_completion, name).offset
+
+
+def test_launch_rules(tmp_path):
+    # default overlaps and the batch kernel's grid rule (vit_shapes.h), built
+    # with g++ and the sanitizers
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "shapes_check")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-I", CSRC, os.path.join(ROOT, "tests", "shapes_check.cpp"), "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout + r.stderr
