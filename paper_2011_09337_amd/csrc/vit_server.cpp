@@ -370,6 +370,8 @@ void engine_main(vit_server *s) {
       std::lock_guard<std::mutex> lk(s->mu);
       fail_locked(s, VIT_ENOMEM, "engine: host resource failure");
     }
+    // if allocations keep failing, do not spin on them
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
   }
 }
 
