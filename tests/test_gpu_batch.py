@@ -166,6 +166,20 @@ def test_autotune_then_decode(dev):
     b.decode(codes, frames, t_llr, out)  # tune=None: the plan's choices
     torch.cuda.synchronize()
     check_frames(out.cpu().numpy(), frames, llr, chosen)
+    # the choices leave the plan and, handed to a fresh plan, give the same bytes
+    ents = b.tuning()
+    assert len(ents) == 3 and {(e["k"], tuple(e["gens"])) for e in ents} == {(k, g) for k, g in CODES[:3]}
+    for e in ents:
+        cid = [c for c in range(3) if CODES[c] == (e["k"], tuple(e["gens"]))][0]
+        assert (e["L"], e["v"], e["v1"], e["waves_per_block"]) == tuple(chosen[cid])
+        assert e["llr_type"] == vit.VIT_LLR_I8
+    b2 = vit.Batch()
+    b2.set_tuning(ents)
+    out2 = torch.zeros_like(out)
+    b2.decode(codes, frames, t_llr, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    b2.close()
     b.close()
 
 
