@@ -237,7 +237,8 @@ typedef struct {
  * *count receives how many the plan holds.  set: adds or replaces entries
  * with the same (code, llr_type, length_bucket); every entry is validated
  * (code, tuning, llr_type, bucket in [0, 40]) before any is taken, and the
- * first bad one is reported with VIT_EINVAL. */
+ * first bad one is reported with VIT_EINVAL; VIT_ENOMEM if the plan cannot
+ * store them (none is taken then). */
 int vit_plan_get_tuning(const vit_plan *plan, vit_tuning_entry *entries, int32_t max, int32_t *count);
 int vit_plan_set_tuning(vit_plan *plan, const vit_tuning_entry *entries, int32_t count);
 
