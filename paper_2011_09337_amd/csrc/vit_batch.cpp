@@ -620,12 +620,15 @@ static int plan_set_tuning_impl(vit_plan *plan, const vit_tuning_entry *entries,
     if (e.length_bucket < 0 || e.length_bucket > 40)
       return api_fail(VIT_EINVAL, "entry %d: length_bucket %d outside [0, 40]", i, e.length_bucket);
   }
+  // all or nothing: the new table is built aside and swapped in
   vit::alloc_checkpoint();
+  std::map<std::string, vit_tuning_entry> next = plan->tuned;
   for (int32_t i = 0; i < count; ++i) {
     vit_tuning_entry e = entries[i];
     for (int b = e.code.beta; b < 4; ++b) e.code.gen[b] = 0;
-    plan->tuned[tune_key(e.code, e.llr_type, e.length_bucket)] = e;
+    next[tune_key(e.code, e.llr_type, e.length_bucket)] = e;
   }
+  plan->tuned.swap(next);
   return VIT_OK;
 }
 

@@ -280,6 +280,15 @@ def test_tuning_export_import(vit, tmp_path):
                 b.set_tuning([dict(ents[0], length_bucket=3), bad])  # the good first entry is not taken either
             assert ei.value.status == vit.VIT_EINVAL and "entry 1" in vit.vit_last_error(), bad
             assert len(b.tuning()) == 2
+        lib = vit._lib.lib
+        assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+        try:
+            with pytest.raises(vit.VitError) as ei:
+                b.set_tuning([dict(ents[0], length_bucket=3)])
+            assert ei.value.status == vit.VIT_ENOMEM
+        finally:
+            lib.vit_debug_fail_allocations(0)
+        assert sorted(b.tuning(), key=lambda d: d["k"]) == got  # nothing taken
         path = str(tmp_path / "tuning.json")
         b.save_tuning(path, device_name="gpu-a")
         assert b2.load_tuning(path, device_name="gpu-b") == 0 and b2.tuning() == []
