@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define VIT_ABI_VERSION 1
+#define VIT_ABI_VERSION 2
 
 enum {
   VIT_OK = 0,
@@ -101,6 +101,17 @@ typedef struct {
    * most 64 subframes per block (VIT_EUNSUPPORTED otherwise). */
   int32_t subframe_words;
   int32_t subframe_overlap; /* W, inner overlap in survivor words, >= 0 (default 2) */
+  /* Path metrics of the integer inputs (VIT_LLR_I8, VIT_LLR_HARD); both give
+   * the decisions of exact integer arithmetic.  16: 16-bit metrics kept
+   * modulo 2^16, two blocks per wave, compared by the sign of their wrapped
+   * difference (eq. 3 in 16 bits; exact while compared metrics differ by less
+   * than 2^15, which the spread bound (k-1)*2*128*beta + 2^14 guarantees);
+   * blocks up to the LDS limit of two blocks' survivors per wave.  32: the
+   * integers held exactly in fp32 metrics, one block per wave; blocks up to
+   * 2^24 / (128 beta) stages.  0 (default): 16 where the blocks fit, else 32.
+   * Subframe traceback runs with 32 only.  Ignored for FP32 LLRs. */
+  int32_t metric_bits;
+  int32_t reserved2;
 } vit_opts;
 
 /* Decode n information bits from FP32 LLRs with blocks of L core bits and
@@ -199,6 +210,10 @@ typedef struct vit_plan vit_plan;
 int vit_plan_create(vit_plan **plan);
 void vit_plan_destroy(vit_plan *plan);
 
+/* Path metrics of the plan's integer decodes, as vit_opts.metric_bits: 0
+ * (default), 16 or 32.  VIT_EINVAL for other values. */
+int vit_plan_set_metric_bits(vit_plan *plan, int32_t bits);
+
 /* Device workspace bytes that vit_decode_batch needs for these frames.  With
  * tune = NULL the size covers every shape the autotuner may choose. */
 int vit_batch_workspace_size(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
@@ -288,6 +303,8 @@ typedef struct {
                                 request's LLRs and decoded bytes                     */
   size_t host_bytes;
   void *stream;              /* hipStream_t the server works on (NULL = default)     */
+  int32_t metric_bits;       /* integer inputs: as vit_opts.metric_bits (0 default)  */
+  int32_t reserved;
 } vit_server_config;
 
 typedef struct {

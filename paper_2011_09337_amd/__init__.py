@@ -25,14 +25,16 @@ __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Serve
 
 
 def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, subframe_overlap=2, check_finite=False,
-           out=None, stream=None):
+           metric_bits=0, out=None, stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
     values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
     subframe_words F > 0 splits each block's traceback into subframes of F
     survivor words with subframe_overlap words of inner overlap (see
     vit_opts); 0 traces each block back once.  check_finite scans FP32 LLRs
     first and raises VitError(VIT_EINVAL) on a NaN or infinity (the call then
-    waits for the scan).  Returns (or fills) a uint8 device
+    waits for the scan).  metric_bits picks the integer inputs' path metrics
+    (16: modulo 2^16, 32: exact in fp32, 0: 16 where the blocks fit; see
+    vit_opts).  Returns (or fills) a uint8 device
     tensor of ceil(n/8) packed bytes.  Asynchronous on `stream` (default:
     torch's current stream)."""
     import torch
@@ -62,6 +64,7 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, su
     opts.check_finite = 1 if check_finite else 0
     opts.subframe_words = int(subframe_words)
     opts.subframe_overlap = int(subframe_overlap)
+    opts.metric_bits = int(metric_bits)
     if stream is None:
         stream = torch.cuda.current_stream(llr.device)
     opts.stream = stream.cuda_stream
@@ -114,10 +117,12 @@ class Batch:
     The workspace is a torch uint8 tensor sized by vit_batch_workspace_size
     for the largest frame list seen."""
 
-    def __init__(self, device="cuda"):
+    def __init__(self, device="cuda", metric_bits=0):
         self.plan = vit_plan_create()
         self.device = device
         self.ws = None
+        if metric_bits:
+            _lib.vit_plan_set_metric_bits(self.plan, metric_bits)
 
     def close(self):
         if self.plan is not None:
@@ -226,7 +231,7 @@ class Server:
     output bytes (requests address it by byte offset, see `requests`)."""
 
     def __init__(self, codes, host, *, tune=None, llr_type=VIT_LLR_I8, arena_bytes=64 << 20, max_frames=4096,
-                 max_items=65536, max_pending=1 << 20, max_wait_ms=0, device="cuda", stream=None):
+                 max_items=65536, max_pending=1 << 20, max_wait_ms=0, metric_bits=0, device="cuda", stream=None):
         import torch
 
         if not host.is_pinned() or host.dtype != torch.uint8:
@@ -240,6 +245,7 @@ class Server:
         cfg.max_items = max_items
         cfg.max_pending = max_pending
         cfg.max_wait_ms = max_wait_ms
+        cfg.metric_bits = metric_bits
         ws_bytes = vit_server_workspace_size(cfg)
         self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
         self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=device)

@@ -35,7 +35,8 @@ class vit_code(C.Structure):
 class vit_opts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("terminated", C.c_int32),
                 ("v1", C.c_int32), ("check_finite", C.c_int32), ("reserved", C.c_int32),
-                ("stream", C.c_void_p), ("subframe_words", C.c_int32), ("subframe_overlap", C.c_int32)]
+                ("stream", C.c_void_p), ("subframe_words", C.c_int32), ("subframe_overlap", C.c_int32),
+                ("metric_bits", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class vit_tuning_entry(C.Structure):
@@ -63,7 +64,7 @@ class vit_server_config(C.Structure):
                 ("max_items", C.c_int32), ("max_pending", C.c_int32), ("max_wait_ms", C.c_int32),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("host", C.c_void_p), ("host_bytes", C.c_size_t),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("metric_bits", C.c_int32), ("reserved", C.c_int32)]
 
 
 class vit_request(C.Structure):
@@ -114,6 +115,8 @@ _PF = C.POINTER(vit_frame)
 _PT = C.POINTER(vit_tuning)
 lib.vit_plan_create.argtypes = [C.POINTER(C.c_void_p)]
 lib.vit_plan_create.restype = C.c_int
+lib.vit_plan_set_metric_bits.argtypes = [C.c_void_p, C.c_int32]
+lib.vit_plan_set_metric_bits.restype = C.c_int
 lib.vit_plan_destroy.argtypes = [C.c_void_p]
 lib.vit_plan_destroy.restype = None
 lib.vit_batch_workspace_size.argtypes = [_PC, C.c_int32, _PF, C.c_int32, _PT, C.POINTER(C.c_size_t)]
@@ -244,6 +247,10 @@ def vit_plan_create():
     p = C.c_void_p()
     _check(lib.vit_plan_create(C.byref(p)))
     return p
+
+
+def vit_plan_set_metric_bits(plan, bits):
+    return _check(lib.vit_plan_set_metric_bits(plan, int(bits)))
 
 
 def vit_plan_destroy(plan):

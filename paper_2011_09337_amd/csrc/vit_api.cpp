@@ -77,6 +77,24 @@ int check_code(const vit_code *c) {
 
 namespace vit {
 int api_check_code(const vit_code *c) { return check_code(c); }
+
+int integer_shape_precheck(int k, int beta, int llr_type, int metric_bits, int64_t max_block_stages, bool subframes) {
+  if (llr_type == VIT_LLR_F32) return VIT_OK;
+  // gfx950 has 160 KiB of LDS per workgroup; the launch checks the device's own figure
+  const int64_t lds_cap = 160 * 1024;
+  const bool fits16 = !subframes && lds16_bytes_per_wave(k, beta, max_block_stages) <= lds_cap;
+  const bool fits32 = fp32_integer_exact(beta, max_block_stages);
+  if (metric_bits == kMetric32 && !fits32)
+    return api_fail(VIT_EUNSUPPORTED, "int8 block of %lld stages: integers exact in fp32 only below 2^24 / (128 beta)",
+                    (long long)max_block_stages);
+  if (metric_bits == kMetric16 && !fits16)
+    return api_fail(VIT_EUNSUPPORTED, "int8 block of %lld stages: %s", (long long)max_block_stages,
+                    subframes ? "subframe traceback runs with 32-bit metrics only"
+                              : "two blocks' survivors exceed the LDS of a workgroup");
+  if (metric_bits == kMetricAuto && !fits16 && !fits32)
+    return api_fail(VIT_EUNSUPPORTED, "int8 block of %lld stages fits neither integer kernel", (long long)max_block_stages);
+  return VIT_OK;
+}
 }  // namespace vit
 
 namespace {
@@ -140,6 +158,7 @@ vit_opts vit_opts_default(void) {
   o.stream = nullptr;
   o.subframe_words = 0;
   o.subframe_overlap = 2;
+  o.metric_bits = 0;
   return o;
 }
 
@@ -181,6 +200,8 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   if (o.llr_type != VIT_LLR_F32 && o.llr_type != VIT_LLR_I8 && o.llr_type != VIT_LLR_HARD)
     return fail(VIT_EINVAL, "unknown llr_type %d", o.llr_type);
   if (o.check_finite != 0 && o.check_finite != 1) return fail(VIT_EINVAL, "check_finite = %d (0 or 1)", o.check_finite);
+  if (o.metric_bits != 0 && o.metric_bits != 16 && o.metric_bits != 32)
+    return fail(VIT_EINVAL, "metric_bits = %d (0, 16 or 32)", o.metric_bits);
   if (o.subframe_words < 0) return fail(VIT_EINVAL, "subframe_words = %d must be >= 0", o.subframe_words);
   if (o.subframe_words > 0 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
     return fail(VIT_EINVAL, "subframe_overlap = %d outside [0, 2^24]", o.subframe_overlap);
@@ -192,13 +213,9 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   const int64_t llr_bytes = g.N * code->beta * (o.llr_type == VIT_LLR_F32 ? 4 : 1);
   if (llr_bytes >= ((int64_t)1 << 32) || g.N >= ((int64_t)1 << 31))
     return fail(VIT_EUNSUPPORTED, "stream of %lld LLR bytes is too long (limit 2^32)", (long long)llr_bytes);
-  if (o.llr_type != VIT_LLR_F32) {
-    // integer metrics are exact in fp32 while |metric| < 2^24
-    const int64_t bound = g.max_block_stages * 128 * code->beta;
-    if (bound >= ((int64_t)1 << 24))
-      return fail(VIT_EUNSUPPORTED, "int8 block of %lld stages may exceed exact fp32 integers",
-                  (long long)g.max_block_stages);
-  }
+  st = vit::integer_shape_precheck(code->k, code->beta, o.llr_type, o.metric_bits, g.max_block_stages,
+                                   o.subframe_words > 0);
+  if (st) return st;
   vit::DecodeArgs a;
   a.llr = llr;
   a.out = out_bits;
@@ -216,6 +233,7 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   a.max_block_stages = (int32_t)g.max_block_stages;
   a.tb_words = o.subframe_words;
   a.tb_overlap = o.subframe_words > 0 ? o.subframe_overlap : 0;
+  a.metric_bits = o.metric_bits;
   if (o.subframe_words > 0) {
     // a block's words reach from its end to the one holding its first core
     // bit: at most ceil(max_block_stages / G) of them

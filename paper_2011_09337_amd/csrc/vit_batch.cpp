@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "vit.h"
+#include "vit_batch_items.h"
 #include "vit_guard.h"
 #include "vit_internal.h"
 #include "vit_shapes.h"
@@ -47,11 +48,14 @@ struct vit_plan {
     void *out = nullptr;
     void *ws = nullptr;
     int llr_type = -1;
+    int metric_bits = -1;
     int ncodes = 0;
     int dev = -1;
     vit_code codes[vit::kMaxCodes];
     vit_tuning tune[vit::kMaxCodes];
   } key;
+
+  int metric_bits = 0;  // integer inputs: 0 (16-bit where it fits), 16 or 32
 
   // autotuned shapes by (code, LLR type, frame-length bucket)
   std::map<std::string, vit_tuning_entry> tuned;
@@ -63,21 +67,16 @@ struct vit_plan {
   std::vector<std::pair<int64_t, int64_t>> out_ranges;
 };
 
-namespace {
+namespace vit {
 
-using vit::api_fail;
-using vit::kHeaderBytes;
-using vit::kMaxCodes;
-using vit::WorkItem;
-
-bool same_code(const vit_code &a, const vit_code &b) {
+static bool same_code(const vit_code &a, const vit_code &b) {
   if (a.k != b.k || a.beta != b.beta) return false;
   for (int i = 0; i < a.beta; ++i)
     if (a.gen[i] != b.gen[i]) return false;
   return true;
 }
 
-bool same_tuning(const vit_tuning &a, const vit_tuning &b) {
+static bool same_tuning(const vit_tuning &a, const vit_tuning &b) {
   return a.L == b.L && a.v == b.v && a.v1 == b.v1 && a.waves_per_block == b.waves_per_block;
 }
 
@@ -99,20 +98,20 @@ int check_tuning(const vit_tuning &t) {
   return VIT_OK;
 }
 
-int frame_bucket(int64_t mean_n) {
+static int frame_bucket(int64_t mean_n) {
   int b = 0;
   while (b < 40 && ((int64_t)1 << (b + 1)) <= mean_n) ++b;
   return b;
 }
 
-std::string tune_key(const vit_code &c, int llr_type, int bucket) {
+static std::string tune_key(const vit_code &c, int llr_type, int bucket) {
   char buf[128];
   snprintf(buf, sizeof(buf), "k%d b%d g%u,%u,%u,%u t%d n%d", c.k, c.beta, c.gen[0], c.gen[1],
            c.beta > 2 ? c.gen[2] : 0u, c.beta > 3 ? c.gen[3] : 0u, llr_type, bucket);
   return buf;
 }
 
-int check_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes) {
+int check_batch_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes) {
   if (!codes || ncodes < 1 || ncodes > kMaxCodes) return api_fail(VIT_EINVAL, "ncodes = %d outside [1, 8]", ncodes);
   for (int c = 0; c < ncodes; ++c) {
     const int st = vit::api_check_code(&codes[c]);
@@ -127,8 +126,7 @@ int check_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, i
 // the items themselves, each code's run sorted by cost, longest first.
 int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
                     const vit_tuning *shape, int elem_bytes, WorkItem *items, int32_t *header,
-                    int64_t *max_stages, std::vector<WorkItem> *tmp_buf = nullptr,
-                    std::vector<int64_t> *hist_buf = nullptr) {
+                    int64_t *max_stages, WorkItem *tmp, int64_t *hist) {
   int64_t counts[kMaxCodes] = {0};
   for (int32_t f = 0; f < nframes; ++f) {
     const int c = frames[f].code_id;
@@ -169,23 +167,19 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
     }
   }
   // each code's run longest first: a stable counting sort on the cost
-  // (at most L + v stages), linear in the item count
-  std::vector<int64_t> own_hist;
-  std::vector<WorkItem> own_tmp;
-  std::vector<int64_t> &hist = hist_buf ? *hist_buf : own_hist;
-  std::vector<WorkItem> &tmp = tmp_buf ? *tmp_buf : own_tmp;
+  // (at most L + v stages), linear in the item count; tmp holds the longest
+  // run, hist max_stages + 2 counters
   for (int c = 0; c < ncodes; ++c) {
     WorkItem *run = items + offs[c];
     const int64_t cnt = counts[c];
     if (cnt > 1) {
       int32_t maxc = 0;
       for (int64_t i = 0; i < cnt; ++i) maxc = std::max(maxc, run[i].cost);
-      hist.assign((size_t)maxc + 2, 0);
-      for (int64_t i = 0; i < cnt; ++i) ++hist[(size_t)(maxc - run[i].cost) + 1];
-      for (size_t i = 1; i < hist.size(); ++i) hist[i] += hist[i - 1];
-      tmp.resize((size_t)cnt);
-      for (int64_t i = 0; i < cnt; ++i) tmp[(size_t)hist[(size_t)(maxc - run[i].cost)]++] = run[i];
-      std::copy(tmp.begin(), tmp.end(), run);
+      std::fill(hist, hist + maxc + 2, (int64_t)0);
+      for (int64_t i = 0; i < cnt; ++i) ++hist[maxc - run[i].cost + 1];
+      for (int32_t i = 1; i < maxc + 2; ++i) hist[i] += hist[i - 1];
+      for (int64_t i = 0; i < cnt; ++i) tmp[hist[maxc - run[i].cost]++] = run[i];
+      std::copy(tmp, tmp + cnt, run);
     }
     header[kMaxCodes + c] = (int32_t)counts[c];
     header[2 * kMaxCodes + c] = (int32_t)offs[c];
@@ -194,11 +188,8 @@ int64_t build_items(const vit_code *codes, int32_t ncodes, const vit_frame *fram
 }
 
 int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes, int64_t llr_count,
-                 int llr_type, int64_t out_bytes, std::vector<std::pair<int64_t, int64_t>> &outs) {
+                 int llr_type, int64_t out_bytes, std::pair<int64_t, int64_t> *outs) {
   const int elem = llr_type == VIT_LLR_F32 ? 4 : 1;
-  vit::alloc_checkpoint();
-  outs.clear();
-  outs.reserve(nframes);
   for (int32_t f = 0; f < nframes; ++f) {
     const vit_frame &fr = frames[f];
     if (fr.code_id < 0 || fr.code_id >= ncodes) return api_fail(VIT_EINVAL, "frame %d: code_id %d", f, fr.code_id);
@@ -214,13 +205,69 @@ int check_frames(const vit_code *codes, int32_t ncodes, const vit_frame *frames,
       return api_fail(VIT_EUNSUPPORTED, "frame %d is too long", f);
     const int64_t nb = (fr.n + 7) / 8;
     if (fr.out_off + nb > out_bytes) return api_fail(VIT_EINVAL, "frame %d: output beyond the buffer", f);
-    outs.emplace_back(fr.out_off, fr.out_off + nb);
+    outs[f] = std::make_pair(fr.out_off, fr.out_off + nb);
   }
   // frames usually come with increasing outputs: sort only when they do not
-  if (!std::is_sorted(outs.begin(), outs.end())) std::sort(outs.begin(), outs.end());
-  for (size_t i = 1; i < outs.size(); ++i)
+  // (std::sort works in place)
+  if (!std::is_sorted(outs, outs + nframes)) std::sort(outs, outs + nframes);
+  for (int32_t i = 1; i < nframes; ++i)
     if (outs[i].first < outs[i - 1].second) return api_fail(VIT_EINVAL, "frames' output ranges overlap");
   return VIT_OK;
+}
+
+// Kernel order of a batch: the code with the most work per bit (states x rate)
+// first; measured faster than running the codes' kernels side by side.
+void batch_code_order(const vit_code *codes, int32_t ncodes, int *order) {
+  for (int c = 0; c < ncodes; ++c) order[c] = c;
+  std::stable_sort(order, order + ncodes, [&](int x, int y) {
+    return ((int64_t)codes[x].beta << (codes[x].k - 1)) > ((int64_t)codes[y].beta << (codes[y].k - 1));
+  });
+}
+
+}  // namespace vit
+
+namespace {
+
+using vit::api_fail;
+using vit::kHeaderBytes;
+using vit::kMaxCodes;
+using vit::WorkItem;
+using vit::build_items;
+using vit::check_frames;
+using vit::check_tuning;
+using vit::default_tuning;
+using vit::same_code;
+using vit::same_tuning;
+using vit::frame_bucket;
+using vit::tune_key;
+
+int check_args(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes) {
+  return vit::check_batch_args(codes, ncodes, frames, nframes);
+}
+
+// check_frames with the plan's range list as storage
+int check_frames_plan(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                      int32_t nframes, int64_t llr_count, int llr_type, int64_t out_bytes) {
+  vit::alloc_checkpoint();
+  plan->out_ranges.resize((size_t)nframes);
+  return check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges.data());
+}
+
+// build_items with the plan's sort buffers, sized for the largest run and cost
+int64_t build_items_plan(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
+                         int32_t nframes, const vit_tuning *shape, int elem_bytes, WorkItem *items, int32_t *header,
+                         int64_t *max_stages) {
+  int64_t counts[kMaxCodes] = {0};
+  for (int32_t f = 0; f < nframes; ++f) counts[frames[f].code_id] += (frames[f].n + shape[frames[f].code_id].L - 1) / shape[frames[f].code_id].L;
+  int64_t run = 0, cost = 0;
+  for (int c = 0; c < ncodes; ++c) {
+    run = std::max(run, counts[c]);
+    cost = std::max(cost, (int64_t)shape[c].L + shape[c].v);
+  }
+  plan->sort_tmp.resize((size_t)run);
+  plan->sort_hist.resize((size_t)cost + 2);
+  return build_items(codes, ncodes, frames, nframes, shape, elem_bytes, items, header, max_stages,
+                     plan->sort_tmp.data(), plan->sort_hist.data());
 }
 
 int resolve_shapes(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
@@ -315,7 +362,7 @@ static int batch_workspace_size_impl(const vit_code *codes, int32_t ncodes, cons
   for (int32_t f = 0; f < nframes; ++f)
     if (frames[f].code_id < 0 || frames[f].code_id >= ncodes || frames[f].n <= 0)
       return api_fail(VIT_EINVAL, "frame %d: bad code_id or n", f);
-  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, 4, nullptr, nullptr, nullptr);
+  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, 4, nullptr, nullptr, nullptr, nullptr, nullptr);
   *bytes = kHeaderBytes + (size_t)total * sizeof(WorkItem);
   return VIT_OK;
 }
@@ -332,14 +379,19 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
   if (((uintptr_t)workspace & 255u) != 0) return api_fail(VIT_EINVAL, "workspace must be 256-byte aligned");
   if (llr_type != VIT_LLR_F32 && llr_type != VIT_LLR_I8 && llr_type != VIT_LLR_HARD)
     return api_fail(VIT_EINVAL, "unknown llr_type %d", llr_type);
-  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges);
+  st = check_frames_plan(plan, codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
   if (st) return st;
   vit_tuning shape[kMaxCodes];
   st = resolve_shapes(plan, codes, ncodes, frames, nframes, llr_type, tune, shape);
   if (st) return st;
+  for (int c = 0; c < ncodes; ++c) {
+    st = vit::integer_shape_precheck(codes[c].k, codes[c].beta, llr_type, plan->metric_bits,
+                                     (int64_t)shape[c].L + shape[c].v, false);
+    if (st) return st;
+  }
 
   const int elem = llr_type == VIT_LLR_F32 ? 4 : 1;
-  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, elem, nullptr, nullptr, nullptr);
+  const int64_t total = build_items(codes, ncodes, frames, nframes, shape, elem, nullptr, nullptr, nullptr, nullptr, nullptr);
   const size_t need = kHeaderBytes + (size_t)total * sizeof(WorkItem);
   if (workspace_bytes < need)
     return api_fail(VIT_EINVAL, "workspace of %zu bytes, %zu needed", workspace_bytes, need);
@@ -359,16 +411,12 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
   int32_t *header = (int32_t *)stg;
   memset(header, 0, kHeaderBytes);
   int64_t max_stages[kMaxCodes];
-  build_items(codes, ncodes, frames, nframes, shape, elem, (WorkItem *)(stg + kHeaderBytes), header, max_stages,
-              &plan->sort_tmp, &plan->sort_hist);
+  build_items_plan(plan, codes, ncodes, frames, nframes, shape, elem, (WorkItem *)(stg + kHeaderBytes), header,
+                   max_stages);
 
   int dev = 0;
   he = hipGetDevice(&dev);
   if (he != hipSuccess) return vit::api_fail_hip(he, "hipGetDevice");
-
-  for (int c = 0; c < ncodes; ++c)
-    if (llr_type != VIT_LLR_F32 && ((int64_t)shape[c].L + shape[c].v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
-      return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
 
   int ncu = 256;
   he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -380,32 +428,36 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
   key.out = out;
   key.ws = workspace;
   key.llr_type = llr_type;
+  key.metric_bits = plan->metric_bits;
   key.ncodes = ncodes;
   key.dev = dev;
   bool same = plan->have_graph && plan->key.llr == llr && plan->key.out == out && plan->key.ws == workspace &&
-              plan->key.llr_type == llr_type && plan->key.ncodes == ncodes && plan->key.dev == dev;
+              plan->key.llr_type == llr_type && plan->key.metric_bits == plan->metric_bits &&
+              plan->key.ncodes == ncodes && plan->key.dev == dev;
   for (int c = 0; c < ncodes; ++c) {
     key.codes[c] = codes[c];
     key.tune[c] = shape[c];
     if (same) same = same_code(plan->key.codes[c], codes[c]) && same_tuning(plan->key.tune[c], shape[c]);
   }
   auto grid_for = [&](int c) -> unsigned {
-    return vit::batch_grid(header[kMaxCodes + c], shape[c].waves_per_block, (int64_t)shape[c].L + shape[c].v,
-                           plan->bl[c].grid, ncu);
+    return vit::batch_launch_grid(plan->bl[c], header[kMaxCodes + c], (int64_t)shape[c].L + shape[c].v, ncu);
   };
   if (!same) {
+    // The old graph goes first: if planning or building fails below, no
+    // later call may take the reuse branch with a half-updated plan.  The
+    // launch shapes are planned aside and kept only with a complete graph.
+    drop_graph(plan);
     // launch shapes (LDS sized for the longest block a shape can produce)
-    vit::BatchLaunch *bl = plan->bl;
+    vit::BatchLaunch bl[kMaxCodes];
     for (int c = 0; c < ncodes; ++c) {
       int unsupported = 0;
       const char *why = "";
-      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type,
+      he = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, llr_type, plan->metric_bits,
                                   (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &bl[c], &unsupported,
                                   &why);
       if (he != hipSuccess) return vit::api_fail_hip(he, "batch launch planning");
       if (unsupported) return api_fail(VIT_EUNSUPPORTED, "code %d: %s", c, why);
     }
-    drop_graph(plan);
     he = hipGraphCreate(&plan->graph, 0);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphCreate");
     he = hipGraphAddMemcpyNode1D(&plan->copy_node, plan->graph, nullptr, 0, workspace, stg, need,
@@ -415,10 +467,7 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
     // most work per bit (states x rate) first: measured faster than running
     // them side by side
     int order[kMaxCodes];
-    for (int c = 0; c < ncodes; ++c) order[c] = c;
-    std::stable_sort(order, order + ncodes, [&](int x, int y) {
-      return ((int64_t)codes[x].beta << (codes[x].k - 1)) > ((int64_t)codes[y].beta << (codes[y].k - 1));
-    });
+    vit::batch_code_order(codes, ncodes, order);
     hipGraphNode_t prev = plan->copy_node;
     for (int oi = 0; oi < ncodes; ++oi) {
       const int c = order[oi];
@@ -431,7 +480,7 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
       for (int b = 0; b < 4; ++b) args.gen[b] = b < codes[c].beta ? codes[c].gen[b] : 0u;
       plan->kwords[c] = bl[c].lds_words_per_wave;
       void *kargs[] = {&args, &plan->kwords[c]};
-      plan->kgrid[c] = grid_for(c);
+      plan->kgrid[c] = vit::batch_launch_grid(bl[c], header[kMaxCodes + c], (int64_t)shape[c].L + shape[c].v, ncu);
       hipKernelNodeParams kp;
       memset(&kp, 0, sizeof(kp));
       kp.func = const_cast<void *>(bl[c].fn);
@@ -447,7 +496,11 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
       prev = kn;
     }
     he = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
-    if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphInstantiate");
+    if (he != hipSuccess) {
+      drop_graph(plan);
+      return vit::api_fail_hip(he, "hipGraphInstantiate");
+    }
+    for (int c = 0; c < ncodes; ++c) plan->bl[c] = bl[c];
     plan->key = key;
     plan->have_graph = true;
   } else {
@@ -493,7 +546,7 @@ static int plan_autotune_impl(vit_plan *plan, const vit_code *codes, int32_t nco
   if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
   int st = check_args(codes, ncodes, frames, nframes);
   if (st) return st;
-  st = check_frames(codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes, plan->out_ranges);
+  st = check_frames_plan(plan, codes, ncodes, frames, nframes, llr_count, llr_type, out_bytes);
   if (st) return st;
   hipEvent_t e0, e1;
   hipError_t he = hipEventCreate(&e0);
@@ -589,6 +642,14 @@ int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, con
     return plan_autotune_impl(plan, codes, ncodes, frames, nframes, llr, llr_count, llr_type, out, out_bytes,
                               workspace, workspace_bytes, stream, chosen);
   });
+}
+
+int vit_plan_set_metric_bits(vit_plan *plan, int32_t bits) {
+  vit::api_clear_error();
+  if (!plan) return api_fail(VIT_EINVAL, "plan is NULL");
+  if (bits != 0 && bits != 16 && bits != 32) return api_fail(VIT_EINVAL, "metric_bits = %d (0, 16 or 32)", bits);
+  plan->metric_bits = bits;
+  return VIT_OK;
 }
 
 int vit_plan_get_tuning(const vit_plan *plan, vit_tuning_entry *entries, int32_t max, int32_t *count) {

@@ -26,7 +26,14 @@ struct DecodeArgs {
   int32_t max_block_stages;
   int32_t tb_words;      // > 0: traceback in subframes of this many survivor words; 0: one per block
   int32_t tb_overlap;    // inner overlap of a subframe, in survivor words
+  int32_t metric_bits;   // integer inputs: 16 (modulo 2^16 metrics), 32 (exact integers held in fp32), 0 = 16
+                         // where the survivor storage fits, else 32
 };
+
+// Path metrics of the integer kernels (int8 and hard-decision inputs).
+constexpr int kMetricAuto = 0;
+constexpr int kMetric16 = 16;
+constexpr int kMetric32 = 32;
 
 // One work item of a batched decode: one block of one frame.
 struct WorkItem {
@@ -58,6 +65,11 @@ struct BatchArgs {
 // instance: groups of 32 stages x states/8 bytes, rounded up to whole bodies
 // of the unrolled loop.  0 if (k, beta) has no kernel instance.
 int64_t lds_bytes_per_block(int k, int beta, int64_t max_block_stages);
+// The same for a wave of the 16-bit metric kernels, which decodes two blocks
+// at once: one dword per slot per body of up to 16 stages.
+int64_t lds16_bytes_per_wave(int k, int beta, int64_t max_block_stages);
+// Integer metrics exact in fp32: (stages of a block) x 128 x beta < 2^24.
+bool fp32_integer_exact(int beta, int64_t max_block_stages);
 
 // Launch the blocked decoder on `stream`.  Returns hipSuccess or the HIP error.
 // *unsupported is set (and hipSuccess returned) if no kernel instance exists
@@ -71,18 +83,28 @@ struct BatchLaunch {
   unsigned grid, block;      // workgroups, threads per workgroup
   size_t lds;                // dynamic LDS bytes per workgroup
   int lds_words_per_wave;
+  int items_per_wave;        // work items a wave takes at once (2 for the 16-bit metric kernels)
+  int metric_bits;           // 16 or 32 for integer inputs, 0 for FP32
 };
-// Fill *bl for a code (k, beta, generators, int8?) decoding blocks of at most
-// max_block_stages stages with `wpb` waves per workgroup.  Returns hipSuccess;
-// sets *unsupported when the shape is not available.
-hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, int in, int64_t max_block_stages, int wpb,
-                             BatchLaunch *bl, int *unsupported, const char **why);
+// Fill *bl for a code (k, beta, generators, input kind, metric choice as
+// DecodeArgs::metric_bits) decoding blocks of at most max_block_stages
+// stages with `wpb` waves per workgroup.  Returns hipSuccess; sets
+// *unsupported when the shape is not available.
+hipError_t plan_batch_launch(int k, int beta, const uint32_t *gen, int in, int metric_bits, int64_t max_block_stages,
+                             int wpb, BatchLaunch *bl, int *unsupported, const char **why);
+// Workgroups of one batch kernel launch over `count` work items (the grid rule
+// of vit_shapes.h applied to the waves' units of work).
+unsigned batch_launch_grid(const BatchLaunch &bl, int64_t count, int64_t max_block_stages, int num_cu);
 
 // Error reporting shared by the C ABI translation units (thread-local message).
 void api_clear_error();
 int api_fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int api_fail_hip(hipError_t e, const char *what);
 int api_check_code(const vit_code *c);
+// The integer kernels' limits that need no device: VIT_EUNSUPPORTED (with the
+// message set) when no integer kernel can take blocks of max_block_stages
+// stages under the metric choice, VIT_OK otherwise (and for FP32 inputs).
+int integer_shape_precheck(int k, int beta, int llr_type, int metric_bits, int64_t max_block_stages, bool subframes);
 
 // A byte range to copy on the device (either side may be pinned host memory
 // mapped for the device).  32 bytes, the layout the copy kernel reads.

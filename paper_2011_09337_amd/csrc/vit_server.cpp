@@ -67,6 +67,8 @@ int check_config(const vit_server_config *cfg) {
     return api_fail(VIT_EINVAL, "max_items = %d outside [1, 2^24]", cfg->max_items);
   if (cfg->max_pending < 1) return api_fail(VIT_EINVAL, "max_pending = %d must be >= 1", cfg->max_pending);
   if (cfg->max_wait_ms < 0) return api_fail(VIT_EINVAL, "max_wait_ms = %d must be >= 0", cfg->max_wait_ms);
+  if (cfg->metric_bits != 0 && cfg->metric_bits != 16 && cfg->metric_bits != 32)
+    return api_fail(VIT_EINVAL, "metric_bits = %d (0, 16 or 32)", cfg->metric_bits);
   return VIT_OK;
 }
 
@@ -204,8 +206,8 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     for (int b = 0; b < 4; ++b) a.gen[b] = b < s->codes[c].beta ? s->codes[c].gen[b] : 0u;
     int words = s->bl[c].lds_words_per_wave;
     void *kargs[] = {&a, &words};
-    const unsigned grid = vit::batch_grid(it.count[c], (int)(s->bl[c].block / 64),
-                                          (int64_t)s->shape[c].L + s->shape[c].v, s->bl[c].grid, s->num_cu);
+    const unsigned grid =
+        vit::batch_launch_grid(s->bl[c], it.count[c], (int64_t)s->shape[c].L + s->shape[c].v, s->num_cu);
     e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
     if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
   }
@@ -413,8 +415,9 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
     if (t.v < 0 || t.v1 < -1 || t.v1 > t.v) return api_fail(VIT_EINVAL, "code %d: bad overlap (v %d, v1 %d)", c, t.v, t.v1);
     if (t.waves_per_block < 1 || t.waves_per_block > 4)
       return api_fail(VIT_EINVAL, "code %d: waves_per_block = %d outside [1, 4]", c, t.waves_per_block);
-    if (cfg->llr_type != VIT_LLR_F32 && ((int64_t)t.L + t.v) * 128 * codes[c].beta >= ((int64_t)1 << 24))
-      return api_fail(VIT_EUNSUPPORTED, "code %d: int8 block too long for exact fp32 integers", c);
+    st = vit::integer_shape_precheck(codes[c].k, codes[c].beta, cfg->llr_type, cfg->metric_bits, (int64_t)t.L + t.v,
+                                     false);
+    if (st) return st;
   }
   if (!cfg->arena || !cfg->workspace || !cfg->host) return api_fail(VIT_EINVAL, "NULL arena, workspace or host region");
   if ((((uintptr_t)cfg->arena | (uintptr_t)cfg->workspace) & 255u) != 0)
@@ -473,7 +476,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
     s->shape[c] = shape[c];
     int unsupported = 0;
     const char *why = "";
-    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type,
+    e = vit::plan_batch_launch(codes[c].k, codes[c].beta, codes[c].gen, cfg->llr_type, cfg->metric_bits,
                                (int64_t)shape[c].L + shape[c].v, shape[c].waves_per_block, &s->bl[c], &unsupported,
                                &why);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "batch launch planning"));

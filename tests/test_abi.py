@@ -34,13 +34,13 @@ def test_library_exports_every_declared_symbol(vit):
 
 
 def test_abi_version(vit):
-    assert vit.vit_abi_version() == 1
+    assert vit.vit_abi_version() == 2
 
 
 def test_opts_default(vit):
     o = vit.vit_opts_default()
-    assert o.size == 40 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
-    assert o.stream is None and o.subframe_words == 0 and o.subframe_overlap == 2
+    assert o.size == 48 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
+    assert o.stream is None and o.subframe_words == 0 and o.subframe_overlap == 2 and o.metric_bits == 0
 
 
 K7 = (7, (0o171, 0o133))
@@ -117,8 +117,21 @@ def test_unsupported_arguments(vit):
     _expect(vit, U, vit.vit_decode, c, FAKE, 100, 12, 4, 0, FAKE)      # L not a multiple of 8
     o = vit.vit_opts_default()
     o.llr_type = vit.VIT_LLR_I8
-    # int8 metrics must stay exact in fp32: a block of 2^16 stages is refused
+    # integer metrics held in fp32 must stay exact: a block of 2^16 stages is refused
+    o.metric_bits = 32
     _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
+    # 16-bit metrics: two such blocks' survivors (2^16 / 12 words of 256 bytes) exceed any LDS
+    o.metric_bits = 16
+    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
+    o.metric_bits = 0
+    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
+    # subframe traceback has no 16-bit metric kernel
+    o.metric_bits, o.subframe_words = 16, 2
+    _expect(vit, U, vit.vit_decode_ex, c, FAKE, 4096, 256, 35, 0, FAKE, o)
+    for bad in (1, 8, 64, -16):
+        o = vit.vit_opts_default()
+        o.llr_type, o.metric_bits = vit.VIT_LLR_I8, bad
+        _expect(vit, vit.VIT_EINVAL, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
 
 
 def _blocks(n, N, L, v1, v2):
@@ -297,3 +310,4 @@ def test_tuning_export_import(vit, tmp_path):
     finally:
         b.close()
         b2.close()
+
