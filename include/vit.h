@@ -236,6 +236,34 @@ int vit_decode_batch(vit_plan *plan, const vit_code *codes, int32_t ncodes, cons
                      int64_t out_bytes, const vit_tuning *tune, void *workspace, size_t workspace_bytes,
                      void *stream);
 
+/* For callers that cannot allocate: code that must not call hipMalloc or
+ * create graphs (work under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The same decode as vit_decode_batch,
+ * bit for bit, without a plan or workspace: the work list (header and work
+ * items) lives in a fixed device array inside the library of 256 +
+ * VIT_STATIC_BATCH_MAX_ITEMS * 40 bytes (10.5 MB), one copy per GPU the
+ * library runs on, held until the process ends; the host builds it in fixed
+ * host arrays of the same capacity.  The call makes no hipMalloc, hipFree,
+ * hipHostMalloc or graph call and no host heap allocation.
+ * tune: one vit_tuning per code, or NULL for the default shapes (L = 256,
+ * v = 5k for k <= 7 and 8(k-1) above, 1 wave per workgroup; no autotuning).
+ * Limits, checked before any device work: at most
+ * VIT_STATIC_BATCH_MAX_FRAMES frames, VIT_STATIC_BATCH_MAX_ITEMS blocks and
+ * VIT_STATIC_BATCH_MAX_STAGES stages per block (L + v); beyond them the call
+ * returns VIT_EUNSUPPORTED with a message naming the limit.
+ * Ordering: the work list is copied on `stream` and the call waits for that
+ * copy (and so for earlier work on `stream`) before it launches the kernels
+ * asynchronously on `stream`.  Every call on one GPU rewrites that GPU's
+ * array: calls on one GPU must be ordered (the same stream, or synchronised
+ * streams); calls that overlap on one GPU race.  The host side is serialised
+ * by a lock.  Errors as vit_decode_batch. */
+#define VIT_STATIC_BATCH_MAX_ITEMS 262144
+#define VIT_STATIC_BATCH_MAX_FRAMES 65536
+#define VIT_STATIC_BATCH_MAX_STAGES 65536
+int vit_decode_batch_static(const vit_code *codes, int32_t ncodes, const vit_frame *frames, int32_t nframes,
+                            const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out, int64_t out_bytes,
+                            const vit_tuning *tune, void *stream);
+
 /* One autotuned shape as a plan keeps it: the code, the LLR type and the
  * frame-length bucket it applies to (bucket b: the mean length of the batch's
  * frames of that code lies in [2^b, 2^(b+1)); 0 below 2). */

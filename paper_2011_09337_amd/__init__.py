@@ -7,6 +7,7 @@ PyTorch provides device memory and streams.
 """
 from . import _lib
 from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
+                   vit_decode_batch_static,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy, vit_plan_get_tuning, vit_plan_set_tuning,
                    vit_tuning_entry)
 from ._lib import (VIT_EBUSY, VIT_ETIMEDOUT, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
@@ -17,7 +18,7 @@ from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LL
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry, vit_depuncture)
 
 __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Server", "FRAME_DTYPE", "REQUEST_DTYPE", "COMPLETION_DTYPE", "VIT_EBUSY", "VIT_ETIMEDOUT", "codes_array", "frames_array", "tunings_array",
-           "vit_batch_workspace_size", "vit_decode_batch", "vit_plan_autotune", "vit_plan_create",
+           "vit_batch_workspace_size", "vit_decode_batch", "vit_decode_batch_static", "vit_plan_autotune", "vit_plan_create",
            "vit_plan_destroy", "vit_plan_get_tuning", "vit_plan_set_tuning", "vit_tuning_entry", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
            "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8", "VIT_LLR_HARD",

@@ -22,6 +22,9 @@ VIT_TIE_LOWER_PRED = 0
 VIT_LLR_F32 = 0
 VIT_LLR_I8 = 1
 VIT_LLR_HARD = 2
+VIT_STATIC_BATCH_MAX_ITEMS = 262144
+VIT_STATIC_BATCH_MAX_FRAMES = 65536
+VIT_STATIC_BATCH_MAX_STAGES = 65536
 
 STATUS_NAMES = {VIT_OK: "VIT_OK", VIT_EINVAL: "VIT_EINVAL", VIT_EUNSUPPORTED: "VIT_EUNSUPPORTED",
                 VIT_ENOMEM: "VIT_ENOMEM", VIT_EDEVICE: "VIT_EDEVICE", VIT_EBUSY: "VIT_EBUSY",
@@ -124,6 +127,9 @@ lib.vit_batch_workspace_size.restype = C.c_int
 lib.vit_decode_batch.argtypes = [C.c_void_p, _PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P,
                                  C.c_int64, _PT, _P, C.c_size_t, _P]
 lib.vit_decode_batch.restype = C.c_int
+lib.vit_decode_batch_static.argtypes = [_PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64,
+                                        _PT, _P]
+lib.vit_decode_batch_static.restype = C.c_int
 lib.vit_plan_autotune.argtypes = [C.c_void_p, _PC, C.c_int32, _PF, C.c_int32, _P, C.c_int64, C.c_int32, _P,
                                   C.c_int64, _P, C.c_size_t, _P, _PT]
 lib.vit_plan_autotune.restype = C.c_int
@@ -283,6 +289,12 @@ def vit_decode_batch(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, 
     return _check(lib.vit_decode_batch(plan, codes_arr, len(codes_arr), _fp(frames_arr), len(frames_arr), llr_ptr,
                                        llr_count, llr_type, out_ptr, out_bytes, tune_arr, ws_ptr, ws_bytes,
                                        stream))
+
+
+def vit_decode_batch_static(codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, tune_arr=None,
+                            stream=None):
+    return _check(lib.vit_decode_batch_static(codes_arr, len(codes_arr), _fp(frames_arr), len(frames_arr), llr_ptr,
+                                              llr_count, llr_type, out_ptr, out_bytes, tune_arr, stream))
 
 
 def vit_plan_autotune(plan, codes_arr, frames_arr, llr_ptr, llr_count, llr_type, out_ptr, out_bytes, ws_ptr,

@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["vit_api.cpp", "vit_batch.cpp", "vit_server.cpp", "vit_launch.hip", "vit_quantize.hip", "vit_copy.hip", "vit_depuncture.hip", "vit_check.hip"] + [f"vit_kernels_k{k}.hip" for k in range(3, 10)] + [f"vit_kernels_sub_k{k}.hip" for k in range(3, 10)] + [f"vit_kernels16_k{k}.hip" for k in range(3, 10)]
+SOURCES = ["vit_api.cpp", "vit_batch.cpp", "vit_batch_static.cpp", "vit_server.cpp", "vit_launch.hip", "vit_quantize.hip", "vit_copy.hip", "vit_depuncture.hip", "vit_check.hip"] + [f"vit_kernels_k{k}.hip" for k in range(3, 10)] + [f"vit_kernels_sub_k{k}.hip" for k in range(3, 10)] + [f"vit_kernels16_k{k}.hip" for k in range(3, 10)]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

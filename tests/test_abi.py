@@ -311,3 +311,31 @@ def test_tuning_export_import(vit, tmp_path):
         b.close()
         b2.close()
 
+
+def test_static_batch_limits_checked_before_device_work(vit):
+    """vit_decode_batch_static refuses batches beyond its fixed arrays with
+    VIT_EUNSUPPORTED and a message naming the limit, before any HIP call (the
+    buffers here are never dereferenced)."""
+    lib = vit._lib
+    codes = vit.codes_array([_code(vit)])
+    U = vit.VIT_EUNSUPPORTED
+
+    def call(frames, tune, llr_count, out_bytes):
+        vit.vit_decode_batch_static(codes, vit.frames_array(frames), FAKE, llr_count, vit.VIT_LLR_F32, FAKE,
+                                    out_bytes, vit.tunings_array(tune) if tune else None)
+
+    n = 8 * (lib.VIT_STATIC_BATCH_MAX_ITEMS + 1)  # one block more than the array holds at L = 8
+    with pytest.raises(vit.VitError) as ei:
+        call([(0, 1, n, 0, 0)], [(8, 0, -1, 1)], (n + 6) * 2, (n + 7) // 8)
+    assert ei.value.status == U and "VIT_STATIC_BATCH_MAX_ITEMS" in vit.vit_last_error()
+    nf = lib.VIT_STATIC_BATCH_MAX_FRAMES + 1
+    frames = [(0, 1, 8, 16 * i, i) for i in range(nf)]
+    with pytest.raises(vit.VitError) as ei:
+        call(frames, None, 16 * nf, nf)
+    assert ei.value.status == U and "VIT_STATIC_BATCH_MAX_FRAMES" in vit.vit_last_error()
+    with pytest.raises(vit.VitError) as ei:
+        call([(0, 1, 100, 0, 0)], [(lib.VIT_STATIC_BATCH_MAX_STAGES, 8, -1, 1)], 212, 13)
+    assert ei.value.status == U and "VIT_STATIC_BATCH_MAX_STAGES" in vit.vit_last_error()
+    # argument errors as vit_decode_batch
+    _expect(vit, vit.VIT_EINVAL, call, [(1, 1, 100, 0, 0)], None, 212, 13)   # code_id outside the codes
+    _expect(vit, vit.VIT_EINVAL, call, [(0, 1, 100, 0, 0)], None, 100, 13)   # LLRs beyond the buffer
