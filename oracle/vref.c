@@ -388,6 +388,128 @@ DEFINE_WINDOW_SPLIT(window_split_i8, int64_t, int8_t, I64_NEG_INF, add_i64, bm_i
 DEFINE_BLOCKED_SPLIT(vref_decode_blocked_split_f32, window_split_f32, float)
 DEFINE_BLOCKED_SPLIT(vref_decode_blocked_split_i8, window_split_i8, int8_t)
 
+/* SplitMix64 (see vref.h): the sequential generator adds the golden-ratio
+ * increment to its state and returns the mixed state, so output i is the mix
+ * of seed + (i + 1) * increment. */
+uint64_t vref_splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Sec. IV-D, first parallel traceback, as vref.h states it.  The forward
+ * procedure is DEFINE_WINDOW's (Algorithm 1 over [s, e)); after each stage
+ * x_c - 1 at which an inner chain (x_c < e) starts, the metrics are kept
+ * (the paper's second start-state solution keeps only their best state; the
+ * whole vector is kept here and reduced when the chain starts).  Then every
+ * subframe runs Algorithm 2 from its own start, emitting only its own bits. */
+#define DEFINE_WINDOW_PT(NAME, T, LT, NEG_INF, ADD, BM)                                        \
+  static int NAME(const vref_code *c, const LT *llr, int64_t s, int64_t e, int start_known,     \
+                  int end_zero, int64_t cs, int64_t ce, int64_t f0, int64_t w, int start_rule,  \
+                  uint64_t seed, int64_t block, uint8_t *out) {                                 \
+    trellis tr;                                                                                \
+    build_trellis(c, &tr);                                                                     \
+    const int S = tr.S, kk = c->k, beta = c->beta;                                             \
+    const int words = (S + 63) / 64;                                                           \
+    const int64_t nst = e - s;                                                                 \
+    const int64_t C = (ce - cs + f0 - 1) / f0;                                                 \
+    int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (size_t)C);                               \
+    T *pm = (T *)malloc(sizeof(T) * (size_t)S);                                                \
+    T *nm = (T *)malloc(sizeof(T) * (size_t)S);                                                \
+    T *snap = (T *)malloc(sizeof(T) * (size_t)S * (size_t)C);                                  \
+    uint64_t *dec = (uint64_t *)calloc((size_t)(nst > 0 ? nst : 1) * (size_t)words,            \
+                                       sizeof(uint64_t));                                      \
+    if (!x || !pm || !nm || !snap || !dec) {                                                   \
+      free(x);                                                                                 \
+      free(pm);                                                                                \
+      free(nm);                                                                                \
+      free(snap);                                                                              \
+      free(dec);                                                                               \
+      return -2;                                                                               \
+    }                                                                                          \
+    for (int64_t ch = 0; ch < C; ++ch) {                                                       \
+      const int64_t b_end = (cs + (ch + 1) * f0 < ce) ? cs + (ch + 1) * f0 : ce;               \
+      x[ch] = (ch == C - 1 || b_end + w >= e) ? e : b_end + w;                                 \
+    }                                                                                          \
+    for (int j = 0; j < S; ++j) pm[j] = start_known ? (j == 0 ? (T)0 : NEG_INF) : (T)0;       \
+    for (int64_t t = s; t < e; ++t) {                                                          \
+      const LT *l = llr + t * beta;                                                            \
+      uint64_t *dt = dec + (t - s) * words;                                                    \
+      for (int j = 0; j < S; ++j) {                                                            \
+        const T m0 = ADD(pm[tr.pred[j][0]], BM(l, beta, tr.aout[j][0]));                       \
+        const T m1 = ADD(pm[tr.pred[j][1]], BM(l, beta, tr.aout[j][1]));                       \
+        const int d = m1 > m0;                                                                 \
+        nm[j] = d ? m1 : m0;                                                                   \
+        if (d) dt[j >> 6] |= 1ull << (j & 63);                                                 \
+      }                                                                                        \
+      T *tmp = pm;                                                                             \
+      pm = nm;                                                                                 \
+      nm = tmp;                                                                                \
+      /* the metrics after stage t, for every inner chain that starts there */                \
+      for (int64_t ch = 0; ch < C; ++ch)                                                       \
+        if (x[ch] < e && x[ch] - 1 == t)                                                       \
+          for (int j = 0; j < S; ++j) snap[ch * S + j] = pm[j];                                \
+    }                                                                                          \
+    for (int64_t ch = 0; ch < C; ++ch) {                                                       \
+      const int64_t a_lo = cs + ch * f0;                                                       \
+      const int64_t b_end = (a_lo + f0 < ce) ? a_lo + f0 : ce;                                 \
+      int j = 0;                                                                               \
+      if (x[ch] == e) {                                                                        \
+        if (!end_zero)                                                                         \
+          for (int i = 1; i < S; ++i)                                                          \
+            if (pm[i] > pm[j]) j = i;                                                          \
+      } else if (start_rule == VREF_PT_RANDOM) {                                               \
+        j = (int)(vref_splitmix64(seed, ((uint64_t)block << 32) | (uint64_t)ch) >> (65 - kk)); \
+      } else {                                                                                 \
+        const T *mt = snap + ch * S;                                                           \
+        for (int i = 1; i < S; ++i)                                                            \
+          if (mt[i] > mt[j]) j = i;                                                            \
+      }                                                                                        \
+      for (int64_t t = x[ch] - 1; t >= a_lo; --t) {                                            \
+        if (t < b_end) out[t - cs] = (uint8_t)(j >> (kk - 2));                                 \
+        const int d = (int)((dec[(t - s) * words + (j >> 6)] >> (j & 63)) & 1u);               \
+        j = ((j << 1) & (S - 1)) | d;                                                          \
+      }                                                                                        \
+    }                                                                                          \
+    free(x);                                                                                   \
+    free(pm);                                                                                  \
+    free(nm);                                                                                  \
+    free(snap);                                                                                \
+    free(dec);                                                                                 \
+    return 0;                                                                                  \
+  }
+
+DEFINE_WINDOW_PT(window_pt_f32, float, float, -INFINITY, add_f32, bm_f32)
+DEFINE_WINDOW_PT(window_pt_i8, int64_t, int8_t, I64_NEG_INF, add_i64, bm_i8)
+
+#define DEFINE_BLOCKED_PT(NAME, WINDOW, LT)                                                     \
+  int NAME(const vref_code *code, const LT *llr, int64_t n, int32_t terminated, int64_t L,    \
+           int64_t v1, int64_t v2, int64_t f0, int64_t w, int32_t start_rule, uint64_t seed,   \
+           uint8_t *out, int32_t nthreads) {                                                   \
+    if (!code_ok(code) || n <= 0 || !llr || !out || L <= 0 || v1 < 0 || v2 < 0 || f0 < 1 ||   \
+        w < 0 || (start_rule != VREF_PT_STORED && start_rule != VREF_PT_RANDOM) ||             \
+        (L + f0 - 1) / f0 > ((int64_t)1 << 32))                                                \
+      return -1;                                                                               \
+    const int64_t N = n + (terminated ? code->k - 1 : 0);                                      \
+    const int64_t nblocks = (n + L - 1) / L;                                                   \
+    int err = 0;                                                                               \
+    if (nthreads < 1) nthreads = 1;                                                            \
+    _Pragma("omp parallel for num_threads(nthreads) schedule(dynamic, 8) reduction(|:err)")    \
+    for (int64_t b = 0; b < nblocks; ++b) {                                                    \
+      const int64_t cs = b * L;                                                                \
+      const int64_t ce = (cs + L < n) ? cs + L : n;                                            \
+      const int64_t s = (cs - v1 > 0) ? cs - v1 : 0;                                           \
+      const int64_t e = (ce + v2 < N) ? ce + v2 : N;                                           \
+      err |= WINDOW(code, llr, s, e, s == 0, terminated && e == N, cs, ce, f0, w, start_rule,  \
+                    seed, b, out + cs);                                                        \
+    }                                                                                          \
+    return err ? -2 : 0;                                                                       \
+  }
+
+DEFINE_BLOCKED_PT(vref_decode_blocked_pt_f32, window_pt_f32, float)
+DEFINE_BLOCKED_PT(vref_decode_blocked_pt_i8, window_pt_i8, int8_t)
+
 int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q) {
   if (count < 0 || (count > 0 && (!llr || !q))) return -1;
   for (int64_t i = 0; i < count; ++i) {
@@ -427,7 +549,16 @@ DEFINE_DEPUNCTURE(vref_depuncture_i8, int8_t)
 int vref_bruteforce_window(const vref_code *code, const double *llr, int64_t s,
                            int64_t e, int32_t start_known, int32_t end_zero,
                            uint8_t *out, double *best_metric) {
-  if (!code_ok(code) || !llr || !out || s < 0 || e <= s) return -1;
+  return vref_bruteforce_window_to(code, llr, s, e, start_known, end_zero ? 0 : -1, out,
+                                   best_metric);
+}
+
+int vref_bruteforce_window_to(const vref_code *code, const double *llr, int64_t s,
+                              int64_t e, int32_t start_known, int32_t end_state,
+                              uint8_t *out, double *best_metric) {
+  if (!code_ok(code) || !llr || !out || s < 0 || e <= s || end_state < -1 ||
+      end_state >= (1 << (code->k - 1)))
+    return -1;
   const int km1 = code->k - 1;
   const int64_t w = e - s;
   const int64_t nbits = km1 + w;
@@ -442,8 +573,12 @@ int vref_bruteforce_window(const vref_code *code, const double *llr, int64_t s,
     int ok = 1;
     if (start_known)
       for (int p = 0; p < km1; ++p) ok &= (x[p] == 0);
-    if (end_zero)
-      for (int64_t p = nbits - km1; p < nbits; ++p) ok &= (x[p] == 0);
+    if (end_state >= 0) {
+      /* the state after the last stage: its last k-1 inputs, newest in the MSB */
+      int st = 0;
+      for (int m = 0; m < km1; ++m) st |= (int)x[nbits - 1 - m] << (km1 - 1 - m);
+      ok &= (st == end_state);
+    }
     if (!ok) continue;
     double metric = 0.0;
     for (int64_t tp = 0; tp < w; ++tp) {

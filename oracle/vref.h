@@ -112,6 +112,39 @@ int vref_decode_blocked_split_i8(const vref_code *code, const int8_t *llr, int64
                                  int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W,
                                  uint8_t *out, int32_t nthreads);
 
+/* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014) used as a counter-based generator: output i of
+ * the sequential generator seeded with `seed` (i = 0, 1, ...), that is
+ * mix(seed + (i + 1) * 0x9E3779B97F4A7C15) with the published mix function. */
+uint64_t vref_splitmix64(uint64_t seed, uint64_t i);
+
+/* Start rules of the parallel traceback's inner chains (Sec. IV-D). */
+enum { VREF_PT_STORED = 0, VREF_PT_RANDOM = 1 };
+
+/* Blocked decoding with the first parallel traceback of Sec. IV-D, in the
+ * paper's geometry.  Block geometry as vref_decode_blocked_*: block b has
+ * stages [s, e) and core [cs, ce).  The core is cut into C = ceil((ce-cs)/f0)
+ * subframes of f0 bits, subframe c = [a_c, b_c) = [cs + c*f0, min(cs +
+ * (c+1)*f0, ce)).  Its traceback starts after stage x_c - 1, runs down to
+ * its first bit and keeps only its own bits, where
+ *   x_c = e                  for the last subframe (the block's own right
+ *                            overlap above it),
+ *   x_c = min(e, b_c + w)    for the others (w stages of overlap into the
+ *                            right neighbour).
+ * Start state: at x_c = e the block's own (state 0 at the end of a
+ * terminated stream, else the best final state, lowest index on ties);
+ * otherwise, with start_rule VREF_PT_STORED the state with the best metric
+ * after stage x_c - 1 (lowest index on ties), with VREF_PT_RANDOM the state
+ * given by the top k-1 bits of vref_splitmix64(seed, (b << 32) | c).
+ * f0 >= L with w >= v2 gives vref_decode_blocked_*.  Requires f0 >= 1,
+ * w >= 0 and at most 2^32 subframes per block. */
+int vref_decode_blocked_pt_f32(const vref_code *code, const float *llr, int64_t n, int32_t terminated,
+                               int64_t L, int64_t v1, int64_t v2, int64_t f0, int64_t w, int32_t start_rule,
+                               uint64_t seed, uint8_t *out, int32_t nthreads);
+int vref_decode_blocked_pt_i8(const vref_code *code, const int8_t *llr, int64_t n, int32_t terminated,
+                              int64_t L, int64_t v1, int64_t v2, int64_t f0, int64_t w, int32_t start_rule,
+                              uint64_t seed, uint8_t *out, int32_t nthreads);
+
 /* De-puncturing (Sec. IV-E): expand a punctured stream into `stages` stages
  * of beta LLRs.  mask[p*beta + b] != 0 when output b of stage t with
  * t mod period = p was transmitted; transmitted values are taken from `in`
@@ -133,6 +166,13 @@ int vref_depuncture_i8(const int8_t *in, int64_t in_count, const uint8_t *mask, 
 int vref_bruteforce_window(const vref_code *code, const double *llr, int64_t s,
                            int64_t e, int32_t start_known, int32_t end_zero,
                            uint8_t *out, double *best_metric);
+/* The same search with the state after the window's last stage fixed:
+ * end_state in [0, 2^(k-1)) keeps only the sequences whose last k-1 inputs
+ * form that state (newest input in the MSB); end_state = -1 leaves it free.
+ * end_state = 0 is end_zero = 1 above. */
+int vref_bruteforce_window_to(const vref_code *code, const double *llr, int64_t s,
+                              int64_t e, int32_t start_known, int32_t end_state,
+                              uint8_t *out, double *best_metric);
 
 #ifdef __cplusplus
 }

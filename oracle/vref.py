@@ -59,11 +59,18 @@ def _declare(L):
                                                _P, i32]
     L.vref_depuncture_i8.argtypes = [_P, i64, _P, i32, i32, i64, _P]
     L.vref_decode_full_i16mod.argtypes = [C.POINTER(VrefCode), _P, i64, i32, _P, _P]
+    L.vref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.vref_splitmix64.restype = C.c_uint64
+    for nm in ("vref_decode_blocked_pt_f32", "vref_decode_blocked_pt_i8"):
+        getattr(L, nm).argtypes = [C.POINTER(VrefCode), _P, i64, i32, i64, i64, i64, i64, i64, i32, C.c_uint64,
+                                   _P, i32]
+    L.vref_bruteforce_window_to.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, _P, _P]
     for fn in (L.vref_encode, L.vref_decode_full_f32, L.vref_decode_full_f64, L.vref_decode_full_i8,
                L.vref_decode_blocked_f32, L.vref_decode_blocked_f64, L.vref_decode_blocked_i8,
                L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window, L.vref_depuncture_f32,
                L.vref_depuncture_i8, L.vref_decode_blocked_split_f32, L.vref_decode_blocked_split_i8,
-               L.vref_decode_full_i16mod):
+               L.vref_decode_full_i16mod, L.vref_decode_blocked_pt_f32, L.vref_decode_blocked_pt_i8,
+               L.vref_bruteforce_window_to):
         fn.restype = C.c_int
 
 
@@ -203,3 +210,36 @@ def decode_blocked_split(code, llr, n, L, v1, v2, G, F, W, terminated=True, nthr
     _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), int(L), int(v1), int(v2), int(G), int(F), int(W),
               _ptr(out), int(nthreads)), fn.__name__)
     return out
+
+
+PT_STORED, PT_RANDOM = 0, 1
+
+
+def splitmix64(seed, i):
+    """Output i of SplitMix64 seeded with `seed` (the random start states of
+    the parallel traceback)."""
+    return int(lib().vref_splitmix64(C.c_uint64(seed & (2 ** 64 - 1)), C.c_uint64(i & (2 ** 64 - 1))))
+
+
+def decode_blocked_pt(code, llr, n, L, v1, v2, f0, w, start_rule=PT_STORED, seed=0, terminated=True, nthreads=1):
+    """Blocked decode with the parallel traceback of Sec. IV-D: subframes of
+    f0 core bits, w stages of inner overlap, inner chains started from the
+    stored best state (PT_STORED) or a random one (PT_RANDOM, from seed)."""
+    llr = np.ascontiguousarray(llr)
+    assert llr.size == n_stages(code, n, terminated) * code.beta, "llr size"
+    out = np.zeros(n, dtype=np.uint8)
+    fn = {np.dtype(np.float32): lib().vref_decode_blocked_pt_f32,
+          np.dtype(np.int8): lib().vref_decode_blocked_pt_i8}[llr.dtype]
+    _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), int(L), int(v1), int(v2), int(f0), int(w),
+              int(start_rule), C.c_uint64(seed & (2 ** 64 - 1)), _ptr(out), int(nthreads)), fn.__name__)
+    return out
+
+
+def bruteforce_window_to(code, llr, s, e, start_known, end_state):
+    """Exhaustive search over a window with the final state fixed (-1: free)."""
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    out = np.zeros(e - s, dtype=np.uint8)
+    met = C.c_double()
+    _check(lib().vref_bruteforce_window_to(C.byref(code), _ptr(llr), s, e, int(start_known), int(end_state),
+                                           _ptr(out), C.byref(met)), "vref_bruteforce_window_to")
+    return out, met.value
