@@ -108,7 +108,8 @@ typedef struct {
    * than 2^15, which the spread bound (k-1)*2*128*beta + 2^14 guarantees);
    * blocks up to the LDS limit of two blocks' survivors per wave.  32: the
    * integers held exactly in fp32 metrics, one block per wave; blocks up to
-   * 2^24 / (128 beta) stages.  0 (default): 16 where the blocks fit, else 32.
+   * 2^24 / (128 beta) stages.  0 (default): 32 where the blocks fit, else 16
+   * (32 measured faster on gfx950 at every shape but K=7 r1/2 at L = 256).
    * Subframe traceback runs with 32 only.  Ignored for FP32 LLRs. */
   int32_t metric_bits;
   int32_t reserved2;

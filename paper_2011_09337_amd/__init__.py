@@ -34,7 +34,7 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, su
     vit_opts); 0 traces each block back once.  check_finite scans FP32 LLRs
     first and raises VitError(VIT_EINVAL) on a NaN or infinity (the call then
     waits for the scan).  metric_bits picks the integer inputs' path metrics
-    (16: modulo 2^16, 32: exact in fp32, 0: 16 where the blocks fit; see
+    (16: modulo 2^16, 32: exact in fp32, 0: 32 where the blocks fit; see
     vit_opts).  Returns (or fills) a uint8 device
     tensor of ceil(n/8) packed bytes.  Asynchronous on `stream` (default:
     torch's current stream)."""

@@ -55,7 +55,7 @@ struct vit_plan {
     vit_tuning tune[vit::kMaxCodes];
   } key;
 
-  int metric_bits = 0;  // integer inputs: 0 (16-bit where it fits), 16 or 32
+  int metric_bits = 0;  // integer inputs: 0 (32-bit where it fits, else 16-bit), 16 or 32
 
   // autotuned shapes by (code, LLR type, frame-length bucket)
   std::map<std::string, vit_tuning_entry> tuned;

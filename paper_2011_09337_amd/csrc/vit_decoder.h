@@ -442,6 +442,44 @@ struct Decoder {
     }
   }
 
+  // Rotation of a P-bit slot or state index by r places (0 <= r < P).
+  __device__ __forceinline__ static uint32_t rotr_p(uint32_t x, int r) {
+    return ((x >> r) | (x << ((P - r) % P))) & (uint32_t)(S - 1);
+  }
+  __device__ __forceinline__ static uint32_t rotl_p(uint32_t x, int r) {
+    return ((x << r) | (x >> ((P - r) % P))) & (uint32_t)(S - 1);
+  }
+
+  // Slot holding the best state after the step at body offset G (any G):
+  // slot j then holds state rotr^(G+1)(j) with the sign convention of phase
+  // G mod P; largest metric, lowest state index on ties.  Uniform.
+  template <int G>
+  __device__ __forceinline__ int best_slot_after() const {
+    constexpr int qg = G % P, rot = (G + 1) % P;
+    float best = -INFINITY;
+    int lab = 0x7fffffff;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int slot = ((reg << 6) | slot0) & (S - 1);
+      const int label = (int)rotr_p((uint32_t)slot, rot);
+      const float sig = ((slot >> qg) & 1) ? -o[reg] : o[reg];
+      if (reg == 0 || sig > best || (sig == best && label < lab)) {
+        best = sig;
+        lab = label;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const float ob = __shfl_xor(best, m);
+      const int ol = __shfl_xor(lab, m);
+      if (ob > best || (ob == best && ol < lab)) {
+        best = ob;
+        lab = ol;
+      }
+    }
+    return (int)rotl_p((uint32_t)__builtin_amdgcn_readfirstlane(lab), rot);
+  }
+
   // Slot index of the best state at a body end, where slot j holds state j
   // with the sign convention of the body's last phase; lowest index on ties.
   // Uniform across the wave.

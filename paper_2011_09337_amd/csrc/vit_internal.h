@@ -26,8 +26,8 @@ struct DecodeArgs {
   int32_t max_block_stages;
   int32_t tb_words;      // > 0: traceback in subframes of this many survivor words; 0: one per block
   int32_t tb_overlap;    // inner overlap of a subframe, in survivor words
-  int32_t metric_bits;   // integer inputs: 16 (modulo 2^16 metrics), 32 (exact integers held in fp32), 0 = 16
-                         // where the survivor storage fits, else 32
+  int32_t metric_bits;   // integer inputs: 16 (modulo 2^16 metrics), 32 (exact integers held in fp32), 0 = 32
+                         // where its bound and survivor storage allow, else 16
 };
 
 // Path metrics of the integer kernels (int8 and hard-decision inputs).

@@ -85,15 +85,19 @@ hipError_t device_info() {
 }
 
 // Resolve the integer metric width for a decode of blocks of at most
-// max_block_stages stages: the 16-bit kernels where asked for or (auto) where
-// their survivor storage fits a workgroup's LDS, else the exact-in-fp32
-// integer kernels where their bound holds.  0 = no kernel (why is set).
+// max_block_stages stages: the 16-bit kernels where asked for, the
+// exact-in-fp32 integer kernels where asked for or (auto) where their bound
+// and their survivor storage allow, else (auto) the 16-bit kernels where two
+// blocks' survivors fit a workgroup's LDS.  Auto prefers the 32-bit kernels
+// because they measured faster on gfx950 (the 16-bit kernels hold two
+// blocks' survivors per wave, which halves the waves the LDS admits).
+// -1 = no kernel (why is set).
 int resolve_metric(int k, int beta, int in, int metric_bits, int64_t max_block_stages, const char **why) {
   if (in == VIT_LLR_F32) return 0;
   const bool fits16 = lds16_bytes_per_wave(k, beta, max_block_stages) <= t_dev.max_lds;
   const bool fits32 = lds_bytes_per_block(k, beta, max_block_stages) <= t_dev.max_lds &&
                       fp32_integer_exact(beta, max_block_stages);
-  if (metric_bits == kMetric16 || (metric_bits == kMetricAuto && fits16)) {
+  if (metric_bits == kMetric16 || (metric_bits == kMetricAuto && !fits32 && fits16)) {
     if (!fits16) *why = "the 16-bit metric kernel's survivor storage for two blocks exceeds the per-workgroup LDS";
     return fits16 ? kMetric16 : -1;
   }

@@ -82,24 +82,25 @@ def check_frames(got, frames, llr, tunes):
 TUNE = [(256, 35, -1, 1), (128, 35, 10, 2), (64, 45, -1, 1), (64, 25, -1, 1), (32, 20, -1, 4)]
 
 
-@pytest.mark.parametrize("int8", [False, True])
-def test_batch_mixed_codes_matches_oracle(dev, int8):
+@pytest.mark.parametrize("int8,metric_bits", [(False, 0), (True, 0), (True, 16), (True, 32)])
+def test_batch_mixed_codes_matches_oracle(dev, int8, metric_bits):
     torch, vit = dev
     rng = np.random.default_rng(11 + int8)
     frames, llr, out_bytes, _ = make_batch(rng, 300, [0, 1, 2, 3, 4], 1, 2000, int8=int8)
-    b = vit.Batch()
+    b = vit.Batch(metric_bits=metric_bits)
     got = run_batch(dev, b, frames, llr, out_bytes, None, TUNE)
     check_frames(got, frames, llr, TUNE)
     b.close()
 
 
-def test_batch_hard_decisions_match_oracle(dev):
+@pytest.mark.parametrize("metric_bits", [0, 16])
+def test_batch_hard_decisions_match_oracle(dev, metric_bits):
     # hard-decision frames (one byte per coded bit) against the oracle on +1 / -1
     torch, vit = dev
     rng = np.random.default_rng(19)
     frames, llr, out_bytes, _ = make_batch(rng, 120, [0, 1, 2, 3, 4], 1, 1500)
     hard = synth.hard_bits(llr)
-    b = vit.Batch()
+    b = vit.Batch(metric_bits=metric_bits)
     got = run_batch(dev, b, frames, hard, out_bytes, None, TUNE)
     check_frames(got, frames, np.where(hard != 0, -1, 1).astype(np.int8), TUNE)
     b.close()
@@ -238,10 +239,11 @@ def test_imported_tuning_is_used(dev):
     b.close()
 
 
-def test_batched_configuration_full_size_sampled(dev):
+@pytest.mark.parametrize("metric_bits", [0, 16])
+def test_batched_configuration_full_size_sampled(dev, metric_bits):
     # the 8192-frame mixed-code configuration at its full size, prepared and
     # launched as the benchmark does (int8 quantisation on the device, one
-    # graph launch, the shapes the autotuner picks there); every 8th frame is
+    # graph launch, the shapes the autotuner picks there); every frame is
     # compared with the oracle
     from concurrent.futures import ThreadPoolExecutor
 
@@ -258,8 +260,9 @@ def test_batched_configuration_full_size_sampled(dev):
         vit.vit_quantize_i8(llr_d.data_ptr() + 4 * lo, cnt, sc, q_d.data_ptr() + lo, None)
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
     tunes = [(512, 35, -1, 1), (512, 35, -1, 1), (256, 64, -1, 2)]
-    b = vit.Batch()
-    print(f"[gpu] full-size batch: {len(frames)} frames, {sum(f[2] for f in frames)} bits", flush=True)
+    b = vit.Batch(metric_bits=metric_bits)
+    print(f"[gpu] full-size batch: {len(frames)} frames, {sum(f[2] for f in frames)} bits, "
+          f"metric_bits={metric_bits}", flush=True)
     b.decode(codes, frames, q_d, out, tune=tunes)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
@@ -275,7 +278,7 @@ def test_batched_configuration_full_size_sampled(dev):
                                    v - v // 2, bool(term))
         return synth.pack_bits(bits)
 
-    sample = frames[::8]
+    sample = frames
     with ThreadPoolExecutor(NCPU) as ex:
         wants = list(ex.map(want, sample))
     for fr, w in zip(sample, wants):

@@ -88,8 +88,8 @@ def expected_oracle(frame, tune):
     return synth.pack_bits(vref.decode_blocked(vref.make_code(k, list(gens)), llr, n, L, v1, v - v1, bool(term)))
 
 
-@pytest.mark.parametrize("int8", [True, False])
-def test_mix_equals_alone_and_oracle(dev, int8):
+@pytest.mark.parametrize("int8,metric_bits", [(True, 0), (True, 16), (False, 0)])
+def test_mix_equals_alone_and_oracle(dev, int8, metric_bits):
     torch, vit = dev
     rng = np.random.default_rng(11 if int8 else 12)
     frames = make_frames(rng, 120, 20, 2500, int8)
@@ -98,7 +98,7 @@ def test_mix_equals_alone_and_oracle(dev, int8):
     # a small arena and few slots and items, so that admission waits for
     # memory and long frames span several iterations
     srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8 if int8 else vit.VIT_LLR_F32,
-                     arena_bytes=96 << 10, max_frames=10, max_items=48)
+                     arena_bytes=96 << 10, max_frames=10, max_items=48, metric_bits=metric_bits)
     try:
         order = rng.permutation(len(frames))
         for wave in np.array_split(order, 8):
