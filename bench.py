@@ -51,16 +51,17 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=24)
     ap.add_argument("--ebn0", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true")
-    ap.add_argument("--subframes", default=None, metavar="F:W",
-                    help="headline decode with the subframe traceback: F words per subframe, W words of overlap")
+    ap.add_argument("--subframes", default=None, metavar="F0:W",
+                    help="headline decode with the parallel traceback: subframes of F0 bits, W stages of overlap")
     ap.add_argument("--no-ml-check", action="store_true",
                     help="skip the headline's comparison with the ML reference decode")
     ap.add_argument("--no-subframe-probe", action="store_true",
-                    help="skip the side measurement of the subframe traceback")
+                    help="skip the side measurement of the parallel traceback")
     ap.add_argument("--precision", action="store_true",
                     help="print the int8-vs-FP32 BER sweep (three codes, 0..6 dB) and exit")
     ap.add_argument("--table3", action="store_true",
-                    help="print the BER-gap grid of the subframe traceback (F x W) and exit")
+                    help="print the parallel traceback's grid (f0 x inner overlap): BER gap to ML and throughput, "
+                         "stored and random chain starts, and exit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-frames", type=int, default=8192)
@@ -106,8 +107,14 @@ def source_hash():
 
 
 def subframe_kw(sub):
-    """decode() keywords of an (F, W) subframe setting (None = one trace)."""
-    return {} if sub is None else dict(subframe_words=sub[0], subframe_overlap=sub[1])
+    """decode() keywords of an (f0, w[, start rule]) parallel-traceback
+    setting (None = one trace per block)."""
+    if sub is None:
+        return {}
+    kw = dict(subframe_bits=sub[0], subframe_overlap=sub[1])
+    if len(sub) > 2:
+        kw["subframe_start"] = sub[2]
+    return kw
 
 
 def time_decode(vit, torch, code, llr_d, out_d, n, L, v, steps, warmup, sub=None):
@@ -452,19 +459,23 @@ def bench_serving(vit, torch, args, tunes):
     }
 
 
-def ber_gaps(vit, torch, configs, log2n=24):
+def ber_gaps(vit, torch, configs, log2n=24, time_at=None, grid=(2.5, 3.0, 3.5, 4.0, 4.5, 5.0)):
     """Eb/N0 gap at BER 1e-4 between decoder configurations and maximum-
     likelihood decoding, K=7 r1/2, FP32 LLRs, 2^log2n bits per Eb/N0 point.
     configs: label -> decode keyword arguments (L, v1, v2 and any options).
     The ML reference is the blocked decoder with v1 = v2 = 128, a traceback
-    depth far beyond convergence (tests check it against full-frame ML)."""
+    depth far beyond convergence (tests check it against full-frame ML; on the
+    2^24-bit 3 dB headline stream the benchmark's CPU leg compares it with the
+    oracle's full-frame decode).  time_at: also time every configuration at
+    that Eb/N0 (information Mbps)."""
     import numpy as np
     import synth
     k, gens = synth.CODES["k7r12"]
     code = vit.make_code(k, gens)
     n = 1 << log2n
-    grid = [2.5, 3.0, 3.5, 4.0, 4.5, 5.0]
+    grid = list(grid)
     errs = {}
+    mbps = {}
     out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
     for e in grid:
         bits, llr = synth.make_stream("k7r12", n, e, seed=100 + int(e * 10))
@@ -478,6 +489,19 @@ def ber_gaps(vit, torch, configs, log2n=24):
         errs[("ml", e)] = nerr(512, 128, 128)
         for label, kw in configs.items():
             errs[(label, e)] = nerr(**kw)
+            if time_at is not None and e == time_at:
+                kk = dict(kw)
+                L, v1, v2 = kk.pop("L"), kk.pop("v1"), kk.pop("v2")
+                stream = torch.cuda.current_stream()
+                for _ in range(2):
+                    vit.decode(code, d, n, L, v1 + v2, v1=v1, out=out, stream=stream, **kk)
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                for _ in range(5):
+                    vit.decode(code, d, n, L, v1 + v2, v1=v1, out=out, stream=stream, **kk)
+                s1.record(stream)
+                torch.cuda.synchronize()
+                mbps[label] = round(n / (s0.elapsed_time(s1) / 5 * 1e-3) / 1e6, 1)
         print(f"[ber] Eb/N0 {e} dB done", file=sys.stderr, flush=True)
 
     def ebn0_at(label):
@@ -499,6 +523,7 @@ def ber_gaps(vit, torch, configs, log2n=24):
         "ml_ebn0_at_1e-4": None if ml_at is None else round(float(ml_at), 4),
         "ml_errors": {str(e): errs[("ml", e)] for e in grid},
         "gap_db": table,
+        "mbps": mbps if time_at is not None else None,
     }
 
 
@@ -582,15 +607,26 @@ def table2_configs():
     return {f"v2={v2},f={f}": dict(L=f, v1=v2, v2=v2) for v2 in (10, 20, 30, 40) for f in (32, 64, 128, 256, 512)}
 
 
+TABLE3_F = 304  # the paper's frame of about 300 bits, rounded up to a multiple of 8
+
+
 def table3_configs():
-    """The parallel-traceback grid (Sec. IV-D and its BER table): blocks of
-    f = 256 with v1 = v2 = 20, subframes of F survivor words (30 stages for
-    K=7) with W words of inner overlap, against the one-trace decoder."""
-    c = {"one trace": dict(L=256, v1=20, v2=20)}
-    for W in (0, 1, 2):
-        for F in (1, 2, 4):
-            c[f"W={W},F={F}"] = dict(L=256, v1=20, v2=20, subframe_words=F, subframe_overlap=W)
+    """The parallel traceback's grid (Sec. IV-D; the paper's BER-gap and
+    throughput tables): frames of f = 304 bits with v1 = 20, subframes of f0
+    in {8, ..., 56} bits with w in {25, ..., 45} stages of inner overlap and
+    the same right overlap v2 = w, inner chains started from the stored best
+    state or from a random state; and the one-trace decoder at each v2 = w."""
+    c = {}
+    for w in (25, 30, 35, 40, 45):
+        c[f"one trace,v2={w}"] = dict(L=TABLE3_F, v1=20, v2=w)
+        for f0 in (8, 16, 24, 32, 40, 48, 56):
+            c[f"v2={w},f0={f0}"] = dict(L=TABLE3_F, v1=20, v2=w, subframe_bits=f0, subframe_overlap=w)
+            c[f"v2={w},f0={f0},random"] = dict(L=TABLE3_F, v1=20, v2=w, subframe_bits=f0, subframe_overlap=w,
+                                               subframe_start=1, subframe_seed=12345)
     return c
+
+
+TABLE3_GRID = tuple(2.5 + 0.5 * i for i in range(12))  # 2.5 .. 8.0 dB: the random starts need the high end
 
 
 def main():
@@ -609,7 +645,8 @@ def main():
         print(json.dumps({"table2": ber_gaps(vit, torch, table2_configs())}), flush=True)
         return
     if args.table3:
-        print(json.dumps({"table3": ber_gaps(vit, torch, table3_configs())}), flush=True)
+        print(json.dumps({"table3": ber_gaps(vit, torch, table3_configs(), time_at=3.0, grid=TABLE3_GRID)}),
+              flush=True)
         return
     if args.precision:
         print(json.dumps({"precision": precision_sweep(vit, torch)}), flush=True)
@@ -653,22 +690,25 @@ def main():
     # decoder with v1 = v2 = 128 (the exact full-frame figure comes from the
     # CPU leg below)
     vs_long = None
+    long_bits = None
     if not args.no_ml_check:
         vit.decode(code, llr_d, n, 512, 256, v1=128, out=out_d)
         torch.cuda.synchronize()
-        vs_long = int(np.sum(synth.unpack_bits(out_d.cpu().numpy(), n) != got))
-    # side measurement: one trace per block vs subframes (Sec. IV-D)
+        long_bits = synth.unpack_bits(out_d.cpu().numpy(), n)
+        vs_long = int(np.sum(long_bits != got))
+    # side measurement: one trace per block vs the parallel traceback of
+    # Sec. IV-D (subframes of f0 bits, w stages of inner overlap)
     subframe = None
     if not args.no_subframe_probe:
         subframe = {}
-        for sub in (None, (1, 1), (1, 2), (2, 2), (4, 2), (8, 2)):
+        for sub in (None, (24, 25), (56, 45), (32, 18), (64, 18), (128, 18), (24, 25, 1)):
             ms_w, _ = time_decode(vit, torch, code, llr_d, out_d, n, args.L, v, max(3, args.steps // 2),
                                   args.warmup, sub=sub)
             vit.decode(code, llr_d, n, args.L, v, out=out_d, **subframe_kw(sub))
             torch.cuda.synchronize()
             ber_w = float(np.mean(synth.unpack_bits(out_d.cpu().numpy(), n) != bits))
-            subframe["one" if sub is None else f"F{sub[0]}W{sub[1]}"] = {"mbps": round(n / (ms_w * 1e-3) / 1e6, 1),
-                                                                         "ber": ber_w}
+            tag = "one" if sub is None else f"f0={sub[0]},w={sub[1]}" + (",random" if len(sub) > 2 else "")
+            subframe[tag] = {"mbps": round(n / (ms_w * 1e-3) / 1e6, 1), "ber": ber_w}
 
     llr_bytes = llr.nbytes
     hbm_alg_bytes = llr_bytes + (n + 7) // 8  # LLRs read once + packed output
@@ -688,11 +728,13 @@ def main():
     cpu = None
     vs_ml = None
     ml_ber = None
+    long_vs_ml = None
     if not args.no_cpu:
         res = cpu_baseline(None, llr, n, args.L, v, ml=not args.no_ml_check)
         if "ml_bits" in res:
             vs_ml = int(np.sum(res["ml_bits"] != got))
             ml_ber = float(np.mean(res["ml_bits"] != bits))
+            long_vs_ml = None if long_bits is None else int(np.sum(res["ml_bits"] != long_bits))
         mbps, nb, dt, th = res["all"]
         cpu = {"value": round(mbps, 3), "unit": "Mbps", "cores": th, "kind": "oracle",
                "sample": f"the whole {nb}-bit stream, blocked L={args.L} v={v}, best of 3 passes: {dt:.2f} s "
@@ -725,8 +767,8 @@ def main():
         "config": {"workload": f"K=7 r1/2 (171/133) terminated stream of 2^{args.n_log2} info bits, FP32 LLRs, "
                                f"BPSK/AWGN Eb/N0={args.ebn0} dB; blocked L={args.L}, v={v} (v1={v // 2}, "
                                f"v2={v - v // 2})" + ("" if head_sub is None else
-                                                      f"; traceback in subframes of {head_sub[0]} words, inner "
-                                                      f"overlap {head_sub[1]} words"),
+                                                      f"; parallel traceback in subframes of {head_sub[0]} bits, "
+                                                      f"inner overlap {head_sub[1]} stages"),
                    "n_bits": n, "L": args.L, "v": v, "ebn0_db": args.ebn0,
                    "subframes": None if head_sub is None else list(head_sub)},
         "roofline": roofline,
@@ -734,7 +776,8 @@ def main():
         "ber": ber,
         "bits_differing_from_ml": vs_ml,
         "ml_reference": None if vs_ml is None else
-        {"decoder": "full-frame ML over the whole stream (CPU oracle, float64 metrics)", "ber": ml_ber},
+        {"decoder": "full-frame ML over the whole stream (CPU oracle, float64 metrics)", "ber": ml_ber,
+         "long_overlap_bits_differing": long_vs_ml},
         "bits_differing_from_long_overlap": vs_long,
         "subframe_traceback": subframe,
         "batched": batched,

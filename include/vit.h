@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define VIT_ABI_VERSION 2
+#define VIT_ABI_VERSION 3
 
 enum {
   VIT_OK = 0,
@@ -69,6 +69,8 @@ enum { VIT_TIE_LOWER_PRED = 0 };
  * 0 for coded bit 0 and any other value for coded bit 1, decoded as integer
  * LLRs +1 / -1 (the hard-decision mode of Sec. I and II-C). */
 enum { VIT_LLR_F32 = 0, VIT_LLR_I8 = 1, VIT_LLR_HARD = 2 };
+/* Start rules of the parallel traceback's inner chains (vit_opts). */
+enum { VIT_SUBFRAME_STORED = 0, VIT_SUBFRAME_RANDOM = 1 };
 
 /* A (beta,1,k) code: 3 <= k <= 9, 2 <= beta <= 4, 0 < gen[b] < 2^k. */
 typedef struct {
@@ -88,19 +90,28 @@ typedef struct {
                           * `stream`); 0 (default): LLRs must be finite, unchecked */
   int32_t reserved;
   void *stream;          /* hipStream_t to launch on; NULL = default stream      */
-  /* Subframe traceback (Sec. IV-D).  0 (default): each block is traced back
-   * once from its end.  F > 0: the block's survivor words (G = (k-1) *
-   * floor(32/(k-1)) stages each, counted from the block end down to the one
-   * holding the first core bit) are cut into subframes of F words, each
-   * traced by its own chain: subframe c starts max(cF - W, 0) words below
-   * the end (W = subframe_overlap), from the block's own start state if that
-   * is the end and otherwise from the state with the best metric there
-   * (lowest index on ties), and emits only the bits decided in its own F
-   * words.  The output then differs from the one-trace decode where a
-   * chain's start state is wrong and the overlap does not correct it.  At
-   * most 64 subframes per block (VIT_EUNSUPPORTED otherwise). */
-  int32_t subframe_words;
-  int32_t subframe_overlap; /* W, inner overlap in survivor words, >= 0 (default 2) */
+  /* Parallel traceback (Sec. IV-D, the paper's first scheme).  0 (default):
+   * each block is traced back once from its end.  f0 = subframe_bits > 0:
+   * the block's core [cs, ce) is cut into C = ceil((ce - cs) / f0) subframes
+   * of f0 bits, subframe c = [cs + c*f0, min(cs + (c+1)*f0, ce)), and each
+   * is traced back by its own chain (one lane of the block's wave) that
+   * emits only its own bits.  Chain c starts after stage x_c - 1 with
+   *   x_c = e (the block end) for the last subframe and wherever
+   *         end_c + w >= e, else x_c = end_c + w (end_c = cs + (c+1)*f0,
+   *         w = subframe_overlap stages of inner overlap).
+   * A chain with x_c = e starts from the block's own traceback state (state
+   * 0 at the end of a terminated stream, else the best final state).  Any
+   * other starts, with subframe_start = VIT_SUBFRAME_STORED, from the state
+   * with the best path metric after stage x_c - 1 (lowest index on ties;
+   * the forward pass keeps it), or with VIT_SUBFRAME_RANDOM from the state
+   * given by the top k-1 bits of output i = (b << 32) | c of the SplitMix64
+   * generator seeded with subframe_seed (b = block index; see
+   * vref_splitmix64 in the oracle for the definition).  f0 >= L gives the
+   * one-trace decode.  Requires at most 64 subframes per block, FP32 LLRs or
+   * 32-bit integer metrics (VIT_EUNSUPPORTED otherwise). */
+  int32_t subframe_bits;
+  int32_t subframe_overlap; /* w >= 0, in stages (default 0)                   */
+  int32_t subframe_start;   /* VIT_SUBFRAME_STORED (default) or _RANDOM        */
   /* Path metrics of the integer inputs (VIT_LLR_I8, VIT_LLR_HARD); both give
    * the decisions of exact integer arithmetic.  16: 16-bit metrics kept
    * modulo 2^16, two blocks per wave, compared by the sign of their wrapped
@@ -112,7 +123,7 @@ typedef struct {
    * (32 measured faster on gfx950 at every shape but K=7 r1/2 at L = 256).
    * Subframe traceback runs with 32 only.  Ignored for FP32 LLRs. */
   int32_t metric_bits;
-  int32_t reserved2;
+  uint64_t subframe_seed;   /* seed of VIT_SUBFRAME_RANDOM (default 0)         */
 } vit_opts;
 
 /* Decode n information bits from FP32 LLRs with blocks of L core bits and

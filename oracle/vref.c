@@ -277,117 +277,6 @@ DEFINE_BLOCKED(vref_decode_blocked_f32, window_f32, float)
 DEFINE_BLOCKED(vref_decode_blocked_f64, window_f64, double)
 DEFINE_BLOCKED(vref_decode_blocked_i8, window_i8, int8_t)
 
-/* Sec. IV-D: the traceback of a block split into subframes, each traced by
- * its own chain.  The stages of a block are cut into words of G stages counted
- * from the block end e (G = the survivor word length of the decoder, passed
- * in); M = the number of words down to the one holding the first core bit cs.
- * Subframe c (c = 0 .. C-1, C = ceil(M / F)) is words [cF, (c+1)F): its chain
- * starts s_c = max(cF - W, 0) words below the end, i.e. after stage
- * x_c - 1 with x_c = e - s_c*G, W words of inner overlap above its subframe.
- * A chain starting at the block end (s_c = 0) takes the block's own start
- * state (state 0 at a terminated end, else the best final state); any other
- * starts from the state with the best metric after stage x_c - 1 (lowest
- * index on ties).  Chain c keeps the decisions of its subframe's stages
- * [e - (c+1)FG, e - cFG), which give the bits t in
- * [e - (c+1)FG - (k-1), e - cFG - (k-1)) (chain 0 also the bits above, from
- * its start state).  The window decode is DEFINE_WINDOW's forward pass with
- * the metrics after each stage x_c - 1 kept, followed by the C tracebacks. */
-#define DEFINE_WINDOW_SPLIT(NAME, T, LT, NEG_INF, ADD, BM)                                     \
-  static int NAME(const vref_code *c, const LT *llr, int64_t s, int64_t e, int start_known,     \
-                  int end_zero, int64_t cs, int64_t ce, int64_t G, int64_t F, int64_t W,       \
-                  uint8_t *out) {                                                              \
-    trellis tr;                                                                                \
-    build_trellis(c, &tr);                                                                     \
-    const int S = tr.S, kk = c->k, beta = c->beta;                                             \
-    const int words = (S + 63) / 64;                                                           \
-    const int64_t nst = e - s;                                                                 \
-    const int64_t M = (e - cs + G - 1) / G;                                                    \
-    const int64_t C = (M + F - 1) / F;                                                         \
-    T *pm = (T *)malloc(sizeof(T) * (size_t)S);                                                \
-    T *nm = (T *)malloc(sizeof(T) * (size_t)S);                                                \
-    T *snap = (T *)malloc(sizeof(T) * (size_t)S * (size_t)C);                                  \
-    uint64_t *dec = (uint64_t *)calloc((size_t)(nst > 0 ? nst : 1) * (size_t)words,            \
-                                       sizeof(uint64_t));                                      \
-    if (!pm || !nm || !snap || !dec) {                                                         \
-      free(pm);                                                                                \
-      free(nm);                                                                                \
-      free(snap);                                                                              \
-      free(dec);                                                                               \
-      return -2;                                                                               \
-    }                                                                                          \
-    for (int j = 0; j < S; ++j) pm[j] = start_known ? (j == 0 ? (T)0 : NEG_INF) : (T)0;       \
-    for (int64_t t = s; t < e; ++t) {                                                          \
-      const LT *l = llr + t * beta;                                                            \
-      uint64_t *dt = dec + (t - s) * words;                                                    \
-      for (int j = 0; j < S; ++j) {                                                            \
-        const T m0 = ADD(pm[tr.pred[j][0]], BM(l, beta, tr.aout[j][0]));                       \
-        const T m1 = ADD(pm[tr.pred[j][1]], BM(l, beta, tr.aout[j][1]));                       \
-        const int d = m1 > m0;                                                                 \
-        nm[j] = d ? m1 : m0;                                                                   \
-        if (d) dt[j >> 6] |= 1ull << (j & 63);                                                 \
-      }                                                                                        \
-      T *tmp = pm;                                                                             \
-      pm = nm;                                                                                 \
-      nm = tmp;                                                                                \
-      /* keep the metrics after stage t for every chain that starts there */                  \
-      for (int64_t ch = 1; ch < C; ++ch) {                                                     \
-        const int64_t sw = ch * F - W;                                                         \
-        if (sw > 0 && e - sw * G - 1 == t)                                                     \
-          for (int j = 0; j < S; ++j) snap[ch * S + j] = pm[j];                                \
-      }                                                                                        \
-    }                                                                                          \
-    for (int64_t ch = 0; ch < C; ++ch) {                                                       \
-      const int64_t sw = ch * F - W > 0 ? ch * F - W : 0;                                      \
-      const int64_t x = e - sw * G;                                                            \
-      const int64_t hi = ch == 0 ? e : e - ch * F * G - (kk - 1);                              \
-      int64_t lo = e - (ch + 1) * F * G - (kk - 1);                                            \
-      if (lo < cs) lo = cs;                                                                    \
-      const T *mt = sw > 0 ? snap + ch * S : pm;                                               \
-      int j = 0;                                                                               \
-      if (sw > 0 || !end_zero)                                                                 \
-        for (int i = 1; i < S; ++i)                                                            \
-          if (mt[i] > mt[j]) j = i;                                                            \
-      for (int64_t t = x - 1; t >= lo; --t) {                                                  \
-        if (t < hi && t < ce) out[t - cs] = (uint8_t)(j >> (kk - 2));                          \
-        const int d = (int)((dec[(t - s) * words + (j >> 6)] >> (j & 63)) & 1u);               \
-        j = ((j << 1) & (S - 1)) | d;                                                          \
-      }                                                                                        \
-    }                                                                                          \
-    free(pm);                                                                                  \
-    free(nm);                                                                                  \
-    free(snap);                                                                                \
-    free(dec);                                                                                 \
-    return 0;                                                                                  \
-  }
-
-DEFINE_WINDOW_SPLIT(window_split_f32, float, float, -INFINITY, add_f32, bm_f32)
-DEFINE_WINDOW_SPLIT(window_split_i8, int64_t, int8_t, I64_NEG_INF, add_i64, bm_i8)
-
-#define DEFINE_BLOCKED_SPLIT(NAME, WINDOW, LT)                                                  \
-  int NAME(const vref_code *code, const LT *llr, int64_t n, int32_t terminated, int64_t L,    \
-           int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W, uint8_t *out,              \
-           int32_t nthreads) {                                                                 \
-    if (!code_ok(code) || n <= 0 || !llr || !out || L <= 0 || v1 < 0 || v2 < 0 || G < 1 ||    \
-        F < 1 || W < 0)                                                                        \
-      return -1;                                                                               \
-    const int64_t N = n + (terminated ? code->k - 1 : 0);                                      \
-    const int64_t nblocks = (n + L - 1) / L;                                                   \
-    int err = 0;                                                                               \
-    if (nthreads < 1) nthreads = 1;                                                            \
-    _Pragma("omp parallel for num_threads(nthreads) schedule(dynamic, 8) reduction(|:err)")    \
-    for (int64_t b = 0; b < nblocks; ++b) {                                                    \
-      const int64_t cs = b * L;                                                                \
-      const int64_t ce = (cs + L < n) ? cs + L : n;                                            \
-      const int64_t s = (cs - v1 > 0) ? cs - v1 : 0;                                           \
-      const int64_t e = (ce + v2 < N) ? ce + v2 : N;                                           \
-      err |= WINDOW(code, llr, s, e, s == 0, terminated && e == N, cs, ce, G, F, W, out + cs); \
-    }                                                                                          \
-    return err ? -2 : 0;                                                                       \
-  }
-
-DEFINE_BLOCKED_SPLIT(vref_decode_blocked_split_f32, window_split_f32, float)
-DEFINE_BLOCKED_SPLIT(vref_decode_blocked_split_i8, window_split_i8, int8_t)
-
 /* SplitMix64 (see vref.h): the sequential generator adds the golden-ratio
  * increment to its state and returns the mixed state, so output i is the mix
  * of seed + (i + 1) * increment. */

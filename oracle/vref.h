@@ -96,22 +96,6 @@ int vref_window_f64(const vref_code *code, const double *llr, int64_t s, int64_t
 /* Saturating int8 quantiser: q = clamp(round_half_even(llr * scale), -127, 127). */
 int vref_quantize_i8(const float *llr, int64_t count, float scale, int8_t *q);
 
-/* Blocked decoding with the traceback of each block split into subframes
- * (Sec. IV-D).  Block geometry as vref_decode_blocked_*.  Words of G stages
- * are counted from the block end e; M words reach down to the one holding
- * the first core bit.  Subframe c (c < ceil(M/F)) is words [cF, (c+1)F); its
- * chain starts max(cF - W, 0) words below the end: at the block end with the
- * block's own start state, else from the state with the best metric there
- * (lowest index on ties); it emits the bits whose decisions lie in its
- * subframe (bit t is decided at stage t + k - 1).  F >= M gives
- * vref_decode_blocked_*. */
-int vref_decode_blocked_split_f32(const vref_code *code, const float *llr, int64_t n, int32_t terminated,
-                                  int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W,
-                                  uint8_t *out, int32_t nthreads);
-int vref_decode_blocked_split_i8(const vref_code *code, const int8_t *llr, int64_t n, int32_t terminated,
-                                 int64_t L, int64_t v1, int64_t v2, int64_t G, int64_t F, int64_t W,
-                                 uint8_t *out, int32_t nthreads);
-
 /* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
  * generators", OOPSLA 2014) used as a counter-based generator: output i of
  * the sequential generator seeded with `seed` (i = 0, 1, ...), that is

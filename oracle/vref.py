@@ -53,10 +53,6 @@ def _declare(L):
     L.vref_quantize_i8.argtypes = [_P, i64, C.c_float, _P]
     L.vref_bruteforce_window.argtypes = [C.POINTER(VrefCode), _P, i64, i64, i32, i32, _P, _P]
     L.vref_depuncture_f32.argtypes = [_P, i64, _P, i32, i32, i64, _P]
-    L.vref_decode_blocked_split_f32.argtypes = [C.POINTER(VrefCode), _P, i64, i32, i64, i64, i64, i64, i64, i64,
-                                                _P, i32]
-    L.vref_decode_blocked_split_i8.argtypes = [C.POINTER(VrefCode), _P, i64, i32, i64, i64, i64, i64, i64, i64,
-                                               _P, i32]
     L.vref_depuncture_i8.argtypes = [_P, i64, _P, i32, i32, i64, _P]
     L.vref_decode_full_i16mod.argtypes = [C.POINTER(VrefCode), _P, i64, i32, _P, _P]
     L.vref_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
@@ -68,7 +64,7 @@ def _declare(L):
     for fn in (L.vref_encode, L.vref_decode_full_f32, L.vref_decode_full_f64, L.vref_decode_full_i8,
                L.vref_decode_blocked_f32, L.vref_decode_blocked_f64, L.vref_decode_blocked_i8,
                L.vref_window_f64, L.vref_quantize_i8, L.vref_bruteforce_window, L.vref_depuncture_f32,
-               L.vref_depuncture_i8, L.vref_decode_blocked_split_f32, L.vref_decode_blocked_split_i8,
+               L.vref_depuncture_i8,
                L.vref_decode_full_i16mod, L.vref_decode_blocked_pt_f32, L.vref_decode_blocked_pt_i8,
                L.vref_bruteforce_window_to):
         fn.restype = C.c_int
@@ -196,19 +192,6 @@ def depuncture(received, mask, stages):
     out = np.zeros(stages * beta, dtype=received.dtype)
     fn = {np.dtype(np.float32): lib().vref_depuncture_f32, np.dtype(np.int8): lib().vref_depuncture_i8}[received.dtype]
     _check(fn(_ptr(received), received.size, _ptr(mask), period, beta, stages, _ptr(out)), fn.__name__)
-    return out
-
-
-def decode_blocked_split(code, llr, n, L, v1, v2, G, F, W, terminated=True, nthreads=1):
-    """Blocked decode with each block's traceback split into subframes of F
-    words of G stages, W words of inner overlap (Sec. IV-D)."""
-    llr = np.ascontiguousarray(llr)
-    assert llr.size == n_stages(code, n, terminated) * code.beta, "llr size"
-    out = np.zeros(n, dtype=np.uint8)
-    fn = {np.dtype(np.float32): lib().vref_decode_blocked_split_f32,
-          np.dtype(np.int8): lib().vref_decode_blocked_split_i8}[llr.dtype]
-    _check(fn(C.byref(code), _ptr(llr), n, int(bool(terminated)), int(L), int(v1), int(v2), int(G), int(F), int(W),
-              _ptr(out), int(nthreads)), fn.__name__)
     return out
 
 

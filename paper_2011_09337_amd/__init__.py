@@ -13,6 +13,7 @@ from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_ba
 from ._lib import (VIT_EBUSY, VIT_ETIMEDOUT, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
                    vit_server_workspace_size)
+from ._lib import (VIT_SUBFRAME_RANDOM, VIT_SUBFRAME_STORED)
 from ._lib import (VIT_EDEVICE, VIT_EINVAL, VIT_ENOMEM, VIT_EUNSUPPORTED, VIT_LLR_F32, VIT_LLR_HARD, VIT_LLR_I8, VIT_OK,
                    VIT_TIE_LOWER_PRED, VitError, make_code, vit_abi_version, vit_decode, vit_decode_ex,
                    vit_last_error, vit_opts_default, vit_quantize_i8, vit_query_geometry, vit_depuncture)
@@ -22,16 +23,18 @@ __all__ = ["decode", "quantize", "depuncture", "vit_depuncture", "Batch", "Serve
            "vit_plan_destroy", "vit_plan_get_tuning", "vit_plan_set_tuning", "vit_tuning_entry", "make_code", "vit_quantize_i8", "VitError", "vit_decode", "vit_decode_ex", "vit_query_geometry",
            "vit_last_error", "vit_abi_version", "vit_opts_default", "VIT_OK", "VIT_EINVAL",
            "VIT_EUNSUPPORTED", "VIT_ENOMEM", "VIT_EDEVICE", "VIT_LLR_F32", "VIT_LLR_I8", "VIT_LLR_HARD",
-           "VIT_TIE_LOWER_PRED"]
+           "VIT_TIE_LOWER_PRED", "VIT_SUBFRAME_STORED", "VIT_SUBFRAME_RANDOM"]
 
 
-def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, subframe_overlap=2, check_finite=False,
-           metric_bits=0, out=None, stream=None):
+def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_bits=0, subframe_overlap=0,
+           subframe_start=None, subframe_seed=0, check_finite=False, metric_bits=0, out=None, stream=None):
     """Decode n bits from a device tensor of LLRs (float32 or int8, N*beta
     values, time-major; uint8 = hard decisions, 0 / nonzero per coded bit).
-    subframe_words F > 0 splits each block's traceback into subframes of F
-    survivor words with subframe_overlap words of inner overlap (see
-    vit_opts); 0 traces each block back once.  check_finite scans FP32 LLRs
+    subframe_bits f0 > 0 runs the parallel traceback of Sec. IV-D: subframes
+    of f0 core bits, subframe_overlap stages of inner overlap, inner chains
+    started from the stored best state (subframe_start VIT_SUBFRAME_STORED,
+    the default) or a random one (VIT_SUBFRAME_RANDOM, seeded by
+    subframe_seed); see vit_opts.  0 traces each block back once.  check_finite scans FP32 LLRs
     first and raises VitError(VIT_EINVAL) on a NaN or infinity (the call then
     waits for the scan).  metric_bits picks the integer inputs' path metrics
     (16: modulo 2^16, 32: exact in fp32, 0: 32 where the blocks fit; see
@@ -63,8 +66,10 @@ def decode(code, llr, n, L, v, *, v1=None, terminated=True, subframe_words=0, su
     opts.terminated = 1 if terminated else 0
     opts.v1 = -1 if v1 is None else int(v1)
     opts.check_finite = 1 if check_finite else 0
-    opts.subframe_words = int(subframe_words)
+    opts.subframe_bits = int(subframe_bits)
     opts.subframe_overlap = int(subframe_overlap)
+    opts.subframe_start = VIT_SUBFRAME_STORED if subframe_start is None else int(subframe_start)
+    opts.subframe_seed = int(subframe_seed)
     opts.metric_bits = int(metric_bits)
     if stream is None:
         stream = torch.cuda.current_stream(llr.device)

@@ -19,6 +19,8 @@ VIT_EDEVICE = -4
 VIT_EBUSY = -5
 VIT_ETIMEDOUT = -6
 VIT_TIE_LOWER_PRED = 0
+VIT_SUBFRAME_STORED = 0
+VIT_SUBFRAME_RANDOM = 1
 VIT_LLR_F32 = 0
 VIT_LLR_I8 = 1
 VIT_LLR_HARD = 2
@@ -38,8 +40,8 @@ class vit_code(C.Structure):
 class vit_opts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("llr_type", C.c_int32), ("terminated", C.c_int32),
                 ("v1", C.c_int32), ("check_finite", C.c_int32), ("reserved", C.c_int32),
-                ("stream", C.c_void_p), ("subframe_words", C.c_int32), ("subframe_overlap", C.c_int32),
-                ("metric_bits", C.c_int32), ("reserved2", C.c_int32)]
+                ("stream", C.c_void_p), ("subframe_bits", C.c_int32), ("subframe_overlap", C.c_int32),
+                ("subframe_start", C.c_int32), ("metric_bits", C.c_int32), ("subframe_seed", C.c_uint64)]
 
 
 class vit_tuning_entry(C.Structure):

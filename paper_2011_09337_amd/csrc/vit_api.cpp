@@ -156,8 +156,10 @@ vit_opts vit_opts_default(void) {
   o.v1 = -1;
   o.check_finite = 0;
   o.stream = nullptr;
-  o.subframe_words = 0;
-  o.subframe_overlap = 2;
+  o.subframe_bits = 0;
+  o.subframe_overlap = 0;
+  o.subframe_start = VIT_SUBFRAME_STORED;
+  o.subframe_seed = 0;
   o.metric_bits = 0;
   return o;
 }
@@ -202,9 +204,11 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   if (o.check_finite != 0 && o.check_finite != 1) return fail(VIT_EINVAL, "check_finite = %d (0 or 1)", o.check_finite);
   if (o.metric_bits != 0 && o.metric_bits != 16 && o.metric_bits != 32)
     return fail(VIT_EINVAL, "metric_bits = %d (0, 16 or 32)", o.metric_bits);
-  if (o.subframe_words < 0) return fail(VIT_EINVAL, "subframe_words = %d must be >= 0", o.subframe_words);
-  if (o.subframe_words > 0 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
+  if (o.subframe_bits < 0) return fail(VIT_EINVAL, "subframe_bits = %d must be >= 0", o.subframe_bits);
+  if (o.subframe_bits > 0 && (o.subframe_overlap < 0 || o.subframe_overlap > (1 << 24)))
     return fail(VIT_EINVAL, "subframe_overlap = %d outside [0, 2^24]", o.subframe_overlap);
+  if (o.subframe_bits > 0 && o.subframe_start != VIT_SUBFRAME_STORED && o.subframe_start != VIT_SUBFRAME_RANDOM)
+    return fail(VIT_EINVAL, "unknown subframe_start %d", o.subframe_start);
   Geometry g;
   int st = resolve(code, n, L, v, o.v1, o.terminated, &g);
   if (st) return st;
@@ -214,7 +218,7 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   if (llr_bytes >= ((int64_t)1 << 32) || g.N >= ((int64_t)1 << 31))
     return fail(VIT_EUNSUPPORTED, "stream of %lld LLR bytes is too long (limit 2^32)", (long long)llr_bytes);
   st = vit::integer_shape_precheck(code->k, code->beta, o.llr_type, o.metric_bits, g.max_block_stages,
-                                   o.subframe_words > 0);
+                                   o.subframe_bits > 0);
   if (st) return st;
   vit::DecodeArgs a;
   a.llr = llr;
@@ -231,18 +235,15 @@ static int decode_ex_impl(const vit_code *code, const void *llr, int64_t n, int3
   a.terminated = o.terminated;
   a.llr_type = o.llr_type;
   a.max_block_stages = (int32_t)g.max_block_stages;
-  a.tb_words = o.subframe_words;
-  a.tb_overlap = o.subframe_words > 0 ? o.subframe_overlap : 0;
+  a.sub_bits = o.subframe_bits;
+  a.sub_overlap = o.subframe_bits > 0 ? o.subframe_overlap : 0;
+  a.sub_start = o.subframe_bits > 0 ? o.subframe_start : VIT_SUBFRAME_STORED;
+  a.sub_seed = o.subframe_seed;
   a.metric_bits = o.metric_bits;
-  if (o.subframe_words > 0) {
-    // a block's words reach from its end to the one holding its first core
-    // bit: at most ceil(max_block_stages / G) of them
-    const int64_t G = (int64_t)(code->k - 1) * (32 / (code->k - 1));
-    const int64_t words = (g.max_block_stages + G - 1) / G;
-    if ((words + o.subframe_words - 1) / o.subframe_words > 64)
-      return fail(VIT_EUNSUPPORTED, "%lld survivor words per block in subframes of %d: more than 64 subframes",
-                  (long long)words, o.subframe_words);
-  }
+  // one lane per subframe chain: at most 64 subframes of the longest core
+  if (o.subframe_bits > 0 && (g.L + o.subframe_bits - 1) / o.subframe_bits > 64)
+    return fail(VIT_EUNSUPPORTED, "cores of %lld bits in subframes of %d: more than 64 subframes per block",
+                (long long)g.L, o.subframe_bits);
   if (o.check_finite && o.llr_type == VIT_LLR_F32) {
     int nonfinite = 0;
     const hipError_t ce = vit::check_finite_f32((const float *)llr, g.N * code->beta, (hipStream_t)o.stream, &nonfinite);

@@ -456,26 +456,35 @@ struct Decoder {
   template <int G>
   __device__ __forceinline__ int best_slot_after() const {
     constexpr int qg = G % P, rot = (G + 1) % P;
+    // Two reductions without branches (this runs between trellis steps, with
+    // their pending compare masks live in SGPRs): the largest metric by max,
+    // then the lowest label among the slots holding it by min.
     float best = -INFINITY;
-    int lab = 0x7fffffff;
+    int labs[REGS];
+    float sigs[REGS];
 #pragma unroll
     for (int reg = 0; reg < REGS; ++reg) {
       const int slot = ((reg << 6) | slot0) & (S - 1);
-      const int label = (int)rotr_p((uint32_t)slot, rot);
-      const float sig = ((slot >> qg) & 1) ? -o[reg] : o[reg];
-      if (reg == 0 || sig > best || (sig == best && label < lab)) {
-        best = sig;
-        lab = label;
-      }
+      labs[reg] = (int)rotr_p((uint32_t)slot, rot);
+      sigs[reg] = ((slot >> qg) & 1) ? -o[reg] : o[reg];
+      best = __builtin_fmaxf(best, sigs[reg]);
+    }
+    // (lane exchanges by ds_bpermute at lane ^ m; the compiler's shuffle
+    // helper adds a width compare that does not compile here)
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1)
+      best = __builtin_fmaxf(best, __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                                  (lane ^ m) << 2, __builtin_bit_cast(int, best))));
+    int lab = 0x7fffffff;
+#pragma unroll
+    for (int reg = 0; reg < REGS; ++reg) {
+      const int cand = sigs[reg] == best ? labs[reg] : 0x7fffffff;
+      lab = cand < lab ? cand : lab;
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
-      const float ob = __shfl_xor(best, m);
-      const int ol = __shfl_xor(lab, m);
-      if (ob > best || (ob == best && ol < lab)) {
-        best = ob;
-        lab = ol;
-      }
+      const int ol = __builtin_amdgcn_ds_bpermute((lane ^ m) << 2, lab);
+      lab = ol < lab ? ol : lab;
     }
     return (int)rotl_p((uint32_t)__builtin_amdgcn_readfirstlane(lab), rot);
   }
@@ -590,14 +599,47 @@ struct Decoder {
   }
 };
 
+// SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014) as a counter-based generator: output i (i = 0,
+// 1, ...) of the sequential generator seeded with `seed`, i.e. the published
+// mix function applied to seed + (i + 1) * 0x9E3779B97F4A7C15.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Parallel traceback of Sec. IV-D (SUB instances): subframes of f0 core bits,
+// w stages of inner overlap, inner chains started from the stored best state
+// (VIT_SUBFRAME_STORED) or a random state (VIT_SUBFRAME_RANDOM, SplitMix64 of
+// seed at counter (block << 32) | subframe).
+struct SubframeArgs {
+  int32_t f0, w, start;
+  uint64_t seed;
+  int64_t block;
+};
+
 // The first (partial) body of a block: step G runs only from the entry offset
 // r on (uniform, scalar branches).  Later bodies run every step unguarded.
+// SUB instances take, after step G, the best state an inner subframe chain
+// starts from when its start stage is that step (sr = its body offset).
+#define VIT_SNAP(NN)                                                 \
+  if constexpr (SUB) {                                               \
+    if ((NN) == sr) take_snapshot(D.template best_slot_after<(NN)>()); \
+  }
 #define VIT_G1(NN, M)                                        \
   if constexpr ((NN) < (M)) {                                \
-    if ((NN) >= r) D.template step<(NN)>();                  \
+    if ((NN) >= r) {                                         \
+      D.template step<(NN)>();                               \
+      VIT_SNAP(NN)                                           \
+    }                                                        \
   }
 #define VIT_U1(NN, M)                                        \
-  if constexpr ((NN) < (M)) D.template step<(NN)>();
+  if constexpr ((NN) < (M)) {                                \
+    D.template step<(NN)>();                                 \
+    VIT_SNAP(NN)                                             \
+  }
 #define VIT_X8(X, B, M)                                                                  \
   X(B + 0, M) X(B + 1, M) X(B + 2, M) X(B + 3, M) X(B + 4, M) X(B + 5, M) X(B + 6, M)   \
   X(B + 7, M)
@@ -607,15 +649,16 @@ struct Decoder {
 // start (stage 0) at `llr` and whose decoded bits start (bit 0) at byte `out`;
 // emit core bits [cs, ce).  start_known: the window starts at the frame's
 // first stage (state 0); end_zero: it ends at the last stage of a terminated
-// frame (trace back from state 0).  SUB instances split the traceback into
-// subframes of tb_words groups with tb_overlap groups of inner overlap
-// (Sec. IV-D); others trace each block once (and ignore both).  Stages are
-// frame-local; the caller guarantees (e - s) * beta * sizeof(LLR) < 2^31, cs
-// a multiple of 8, and at most 64 subframes per block.
+// frame (trace back from state 0).  SUB instances run the parallel traceback
+// of Sec. IV-D (sa: subframes of f0 bits, one lane per chain; the caller
+// guarantees at most 64 subframes and ceil((ce - cs) / 4) spare words of LDS
+// after the survivors); others trace each block once from its end.  Stages
+// are frame-local; the caller guarantees (e - s) * beta * sizeof(LLR) <
+// 2^31 and cs a multiple of 8.
 template <bool SUB, int K, int BETA, bool STD, int IN>
 __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, IN> &D, const void *llr, uint8_t *out,
                                              int64_t s, int64_t e, int64_t cs, int64_t ce, bool start_known,
-                                             bool end_zero, int tb_words, int tb_overlap, const uint32_t *gen) {
+                                             bool end_zero, const SubframeArgs &sa, const uint32_t *gen) {
   using Sh = Shape<K, BETA>;
   constexpr int P = Sh::P, S = Sh::S, REGS = Sh::REGS, BODY = Sh::BODY, T = Sh::T;
   (void)T;
@@ -631,22 +674,39 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, IN> &D, const
   D.s_hi = (int)e - 1;
   D.body = 0;
 
-  // Traceback geometry.  Groups (bodies) grp_lo .. nbody-1 hold the stages
-  // from the one with the first core bit to the block end; counted from the
-  // end they are words 0 .. nw-1.  With subframes of F = tb_words words
-  // (Sec. IV-D) there are nch = ceil(nw / F) chains: chain c keeps words
-  // [cF, (c+1)F) and starts sw_c = max(cF - W, 0) words below the end, with
-  // W = tb_overlap words of inner overlap; a chain with sw_c > 0 starts from
-  // the best state at the end of group nbody-1-sw_c, taken when the forward
-  // pass gets there (highest chain first) and kept in lane c of snap_v.
-  const int grp_lo = ((int)(cs - s) + r) / BODY;
-  const int nw = nbody - grp_lo;
-  const int F = SUB && tb_words > 0 ? tb_words : nw;
-  const int W = SUB && tb_words > 0 ? tb_overlap : 0;
-  const int nch = (nw + F - 1) / F;
-  const int c_min = W / F + 1;  // first chain with sw_c > 0
-  int snap_c = nch - 1;
-  int snap_next = snap_c >= c_min ? nbody - 1 - (snap_c * F - W) : -1;
+  // Subframe geometry (Sec. IV-D).  The core [cs, ce) splits into C
+  // subframes of f0 bits; subframe c = [cs + c f0, min(cs + (c+1) f0, ce))
+  // is traced from stage x_c - 1 down, x_c = e for the last one or where its
+  // end plus w reaches e, else its end plus w.  The inner chains (x_c < e)
+  // are c = 0 .. n_inner - 1; with the stored start rule the forward pass
+  // keeps the best state after each stage x_c - 1 in lane c of snap_v.
+  const int f0 = SUB ? sa.f0 : 1;
+  const int C = SUB ? (int)((ce - cs + f0 - 1) / f0) : 1;
+  int n_inner = 0;
+  if constexpr (SUB) {
+    // c < C - 1 and cs + (c + 1) f0 + w < e
+    const int64_t room = e - 1 - sa.w - cs;  // (c + 1) f0 <= room
+    n_inner = room >= f0 ? (int)(room / f0) : 0;
+    if (n_inner > C - 1) n_inner = C - 1;
+  }
+  uint32_t snap_v = 0;
+  int snap_c = 0;
+  // body offset, in the current body, of the next snapshot (none: -1)
+  int64_t snap_rel = (SUB && sa.start == VIT_SUBFRAME_STORED && n_inner > 0)
+                         ? (cs + f0 + sa.w - 1) - D.stage_base : -1;
+  int sr = -1;
+  auto take_snapshot = [&](int slot) {
+    snap_v = D.lane == snap_c ? (uint32_t)slot : snap_v;
+    ++snap_c;
+    if (snap_c < n_inner) {
+      snap_rel += f0;
+      sr += f0;
+    } else {
+      snap_rel = -1;
+      sr = -1;
+    }
+  };
+  (void)take_snapshot;
 
   // Initial metrics: state 0 known at the stream start, else all zero.  The
   // slot holding state rotr^r(slot) keeps it with sign convention of phase r-1.
@@ -674,31 +734,89 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, IN> &D, const
     D.body = 0;
     D.fetch_entry(gen, r, D.xn, D.yn);
   }
-  // At each body end slot j holds state j: subframe start states are taken
-  // there.
-  uint32_t snap_v = 0;
-  auto take_snapshot = [&]() {
-    const uint32_t best = (uint32_t)D.best_state();
-    snap_v = D.lane == snap_c ? best : snap_v;
-    --snap_c;
-    snap_next = snap_c >= c_min ? snap_next + F : -1;
-  };
   D.body = 0;
   D.refresh_addresses();
+  if constexpr (SUB) sr = snap_rel >= 0 && snap_rel < BODY ? (int)snap_rel : -1;
   VIT_X32(VIT_G1, BODY)
-  if constexpr (SUB) {
-    if (snap_next == 0) take_snapshot();
-  }
   for (D.body = 1; D.body < nbody; ++D.body) {
     D.refresh_addresses();
-    VIT_X32(VIT_U1, BODY)
     if constexpr (SUB) {
-      if (D.body == snap_next) take_snapshot();
+      const int64_t rel = snap_rel - (int64_t)D.body * BODY;
+      sr = snap_rel >= 0 && rel < BODY ? (int)rel : -1;
     }
+    VIT_X32(VIT_U1, BODY)
   }
 
   // ---- traceback start: state 0 at a terminated end, else the best state.
   const int lam = end_zero ? 0 : D.best_state();
+
+  if constexpr (SUB) {
+    // ---- parallel traceback (Sec. IV-D): lane c runs subframe c's chain.
+    // The chain holds the slot u of its state after stage t; at a stage of
+    // body offset pos (q = pos mod P) the decoded bit of stage t is bit q of
+    // u (the state's newest input, rotated into place) and following the
+    // survivor flips bit q by the stored word bit (decision XOR own bit q).
+    // Decoded bits go to one LDS byte each, after the survivors.
+    uint8_t *dbytes = (uint8_t *)(D.lds + nbody * REGS * 64);
+    const int c = D.lane;
+    int len = 0, t = 0, b_end = 0, pos = 0, q = 0, bdy = 0;
+    uint32_t u = 0;
+    if (c < C) {
+      const int a_lo = (int)cs + c * f0;
+      b_end = a_lo + f0 < (int)ce ? a_lo + f0 : (int)ce;
+      const bool inner = c < n_inner;
+      const int x = inner ? b_end + sa.w : (int)e;
+      const int rel = x - 1 - (int)D.stage_base;
+      bdy = rel / BODY;
+      pos = rel - bdy * BODY;
+      q = pos % P;
+      if (!inner) {
+        u = (uint32_t)lam;  // the block end is a body end: slot j holds state j
+      } else if (sa.start == VIT_SUBFRAME_RANDOM) {
+        const uint64_t z = splitmix64_at(sa.seed, ((uint64_t)sa.block << 32) | (uint64_t)c);
+        const uint32_t st = (uint32_t)(z >> (65 - K));
+        u = D.rotl_p(st, (pos + 1) % P);
+      } else {
+        u = snap_v;
+      }
+      t = x - 1;
+      len = x - a_lo;
+    }
+    int maxlen = len;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      const int o = __shfl_xor(maxlen, m);
+      maxlen = o > maxlen ? o : maxlen;
+    }
+    maxlen = __builtin_amdgcn_readfirstlane(maxlen);
+    for (int i = 0; i < maxlen; ++i) {
+      if (i < len) {
+        if (t < b_end) dbytes[t - (int)cs] = (uint8_t)((u >> q) & 1u);
+        const uint32_t wd = D.lds[(bdy * REGS + (int)(u >> 6)) * 64 + (int)(u & 63u)];
+        u ^= ((wd >> (BODY - 1 - pos)) & 1u) << q;
+        --t;
+        q = q == 0 ? P - 1 : q - 1;
+        if (--pos < 0) {
+          pos = BODY - 1;
+          --bdy;
+        }
+      }
+    }
+    // ---- output: lane-parallel packing of the decoded bytes (the wave's
+    // LDS writes are complete before its reads).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t b_lo = cs >> 3, b_hi = (ce - 1) >> 3;
+    for (int64_t B = b_lo + D.lane; B <= b_hi; B += 64) {
+      const int base = (int)(8 * B - cs);
+      const int nv = (int)(ce - 8 * B) < 8 ? (int)(ce - 8 * B) : 8;
+      uint32_t byte = 0;
+      for (int j = 0; j < nv; ++j) byte |= (uint32_t)(dbytes[base + j] & 1u) << j;
+      out[B] = (uint8_t)byte;
+    }
+    return;
+  }
 
   // ---- traceback on the scalar unit (Decoder::tb_groups).  The decision bit
   // at offset g is the input bit of offset g - (k-1) (the oldest input of the
@@ -708,62 +826,17 @@ __device__ __forceinline__ void decode_block(Decoder<K, BETA, STD, IN> &D, const
   // The traceback is a short serial chain of scalar steps: raise the wave's
   // issue priority while it runs so that waves in their forward pass do not
   // stretch it (measured: about 8% faster overall).
+  const int grp_lo = ((int)(cs - s) + r) / BODY;
   __builtin_amdgcn_s_setprio(1);
   const uint32_t lam_start = (uint32_t)lam;
-  if (!SUB || nch == 1) {
+  {
     uint32_t u1[1] = {(uint32_t)lam};
     const bool w1[1] = {true};
     for (int grp = nbody - 1; grp >= grp_lo; --grp) {
       const int g1[1] = {grp};
       D.template tb_groups<1>(g1, u1, w1);
     }
-  } else {
-    // Chains go bottom-up in pairs (c, c-1) stepped together.  A chain
-    // rewrites only the words of its own subframe; every chain that reads
-    // them (a lower one, through its overlap) runs in an earlier pair, or in
-    // the same pair at least one step earlier, or at the same step (words are
-    // read before they are written).
-    struct Chain {
-      int top, len, wlim;  // first group traced, groups traced, highest group it writes
-      uint32_t lam;        // start state
-    };
-    auto chain = [&](int ch) {
-      Chain k;
-      const int sw = ch * F - W > 0 ? ch * F - W : 0;
-      const int bottom = ((ch + 1) * F < nw ? (ch + 1) * F : nw) - 1;  // lowest word
-      k.top = nbody - 1 - sw;
-      k.len = bottom - sw + 1;
-      k.wlim = nbody - 1 - ch * F;
-      k.lam = sw > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)snap_v, ch) : (uint32_t)lam;
-      return k;
-    };
-    for (int c = nch - 1; c >= 0; c -= 2) {
-      Chain a = chain(c);
-      int both = 0;
-      if (c >= 1) {
-        Chain b = chain(c - 1);
-        both = a.len < b.len ? a.len : b.len;
-        uint32_t u[2] = {a.lam, b.lam};
-        for (int i = 0; i < both; ++i) {
-          const int g2[2] = {a.top - i, b.top - i};
-          const bool w2[2] = {a.top - i <= a.wlim, b.top - i <= b.wlim};
-          D.template tb_groups<2>(g2, u, w2);
-        }
-        a.lam = u[0];
-        b.lam = u[1];
-        if (b.len > a.len) {  // continue with the longer chain alone
-          a = b;
-        }
-      }
-      uint32_t u1[1] = {a.lam};
-      for (int i = both; i < a.len; ++i) {
-        const int g1[1] = {a.top - i};
-        const bool w1[1] = {a.top - i <= a.wlim};
-        D.template tb_groups<1>(g1, u1, w1);
-      }
-    }
   }
-
   __builtin_amdgcn_s_setprio(0);
 
   // ---- output: lane-parallel assembly of the core bits [cs, ce) into bytes.
@@ -830,8 +903,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!SUB && K >
     const int64_t ce = (cs + a.L < a.n) ? cs + a.L : a.n;
     const int64_t s = (cs - a.v1 > 0) ? cs - a.v1 : 0;
     const int64_t e = (ce + a.v2 < a.N) ? ce + a.v2 : a.N;
-    decode_block<SUB>(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), a.tb_words,
-                      a.tb_overlap, a.gen);
+    const SubframeArgs sa{a.sub_bits, a.sub_overlap, a.sub_start, a.sub_seed, blk};
+    decode_block<SUB>(D, a.llr, a.out, s, e, cs, ce, s == 0, a.terminated && (e == a.N), sa, a.gen);
   }
 }
 
@@ -859,11 +932,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <=
   for (int idx = (int)blockIdx.x * wpb + wid; idx < nitems; idx += nwaves) {
     const WorkItem it = items[idx];
     const char *base = (const char *)a.llr + it.llr_off;
+    const SubframeArgs none{0, 0, 0, 0, 0};
     decode_block<false>(D, (const void *)base, a.out + it.out_off, it.s, it.e, it.cs, it.ce, (it.flags & 1) != 0,
-                        (it.flags & 2) != 0, 0, 0, a.gen);
+                        (it.flags & 2) != 0, none, a.gen);
   }
 }
 
+#undef VIT_SNAP
 #undef VIT_G1
 #undef VIT_U1
 #undef VIT_X8

@@ -24,8 +24,10 @@ struct DecodeArgs {
   int32_t terminated;
   int32_t llr_type;      // VIT_LLR_F32, VIT_LLR_I8 or VIT_LLR_HARD
   int32_t max_block_stages;
-  int32_t tb_words;      // > 0: traceback in subframes of this many survivor words; 0: one per block
-  int32_t tb_overlap;    // inner overlap of a subframe, in survivor words
+  int32_t sub_bits;      // > 0: parallel traceback in subframes of this many core bits; 0: one per block
+  int32_t sub_overlap;   // inner overlap of a subframe, in stages
+  int32_t sub_start;     // VIT_SUBFRAME_STORED or VIT_SUBFRAME_RANDOM
+  uint64_t sub_seed;     // SplitMix64 seed of the random start rule
   int32_t metric_bits;   // integer inputs: 16 (modulo 2^16 metrics), 32 (exact integers held in fp32), 0 = 32
                          // where its bound and survivor storage allow, else 16
 };

@@ -157,7 +157,7 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
     const hipError_t err = device_info();
     if (err != hipSuccess) return err;
   }
-  if (a.llr_type != VIT_LLR_F32 && a.tb_words == 0) {
+  if (a.llr_type != VIT_LLR_F32 && a.sub_bits == 0) {
     const int m = resolve_metric(a.k, a.beta, a.llr_type, a.metric_bits, a.max_block_stages, why);
     if (m < 0) {
       *unsupported = 1;
@@ -179,14 +179,16 @@ hipError_t launch_blocked(const DecodeArgs &a, hipStream_t stream, int *unsuppor
   }
   bool stdc = true;
   for (int b = 0; b < a.beta; ++b) stdc = stdc && ((a.gen[b] >> (a.k - 1)) & 1u) && (a.gen[b] & 1u);
-  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type, a.tb_words > 0);
+  KernelFn fn = pick_kernel(a.k, a.beta, stdc, a.llr_type, a.sub_bits > 0);
   if (!fn) {
     *unsupported = 1;
     *why = "no kernel instance for this (k, beta)";
     return hipSuccess;
   }
   hipError_t err;
-  const int64_t lds_wave = lds_bytes_per_block(a.k, a.beta, a.max_block_stages);
+  // the parallel traceback keeps one decoded byte per core bit after the survivors
+  const int64_t lds_wave = lds_bytes_per_block(a.k, a.beta, a.max_block_stages) +
+                           (a.sub_bits > 0 ? (a.L + 3) / 4 * 4 : 0);
   if (lds_wave > t_dev.max_lds) {
     *unsupported = 1;
     *why = "one block's survivor storage exceeds the per-workgroup LDS";

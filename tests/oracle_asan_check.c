@@ -106,14 +106,15 @@ static void run_code(const code_def *cd, int64_t n, int terminated) {
       CHECK(memcmp(o1, o2, (size_t)n) == 0, "thread count changed the bits");
       CHECK(vref_decode_blocked_f64(&c, ld, n, terminated, L, v1, v2, o1, 2) == 0, "blocked f64");
       CHECK(vref_decode_blocked_i8(&c, lq, n, terminated, L, v1, v2, o1, 2) == 0, "blocked i8");
-      const int64_t G = (int64_t)(c.k - 1) * (32 / (c.k - 1));
-      const int64_t FW[][2] = {{1, 0}, {1, 1}, {2, 2}, {1000, 2}};
-      for (size_t f = 0; f < sizeof(FW) / sizeof(FW[0]); ++f) {
-        CHECK(vref_decode_blocked_split_f32(&c, lf, n, terminated, L, v1, v2, G, FW[f][0], FW[f][1], o1, 2) == 0,
-              "split f32");
-        CHECK(vref_decode_blocked_split_i8(&c, lq, n, terminated, L, v1, v2, 3, FW[f][0], FW[f][1], o2, 1) == 0,
-              "split i8");
-      }
+      const int64_t FW[][2] = {{1, 0}, {1, 1}, {3, 2}, {8, 25}, {1000, 2}};
+      for (size_t f = 0; f < sizeof(FW) / sizeof(FW[0]); ++f)
+        for (int rule = VREF_PT_STORED; rule <= VREF_PT_RANDOM; ++rule) {
+          CHECK(vref_decode_blocked_pt_f32(&c, lf, n, terminated, L, v1, v2, FW[f][0], FW[f][1], rule, 7u, o1, 2) ==
+                    0,
+                "pt f32");
+          CHECK(vref_decode_blocked_pt_i8(&c, lq, n, terminated, L, v1, v2, FW[f][0], FW[f][1], rule, 7u, o2, 1) == 0,
+                "pt i8");
+        }
     }
   /* one window with an emit range inside it */
   if (N >= 4) {

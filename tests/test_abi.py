@@ -34,13 +34,14 @@ def test_library_exports_every_declared_symbol(vit):
 
 
 def test_abi_version(vit):
-    assert vit.vit_abi_version() == 2
+    assert vit.vit_abi_version() == 3
 
 
 def test_opts_default(vit):
     o = vit.vit_opts_default()
-    assert o.size == 48 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
-    assert o.stream is None and o.subframe_words == 0 and o.subframe_overlap == 2 and o.metric_bits == 0
+    assert o.size == 56 and o.llr_type == vit.VIT_LLR_F32 and o.terminated == 1 and o.v1 == -1
+    assert o.stream is None and o.subframe_bits == 0 and o.subframe_overlap == 0 and o.metric_bits == 0
+    assert o.subframe_start == vit.VIT_SUBFRAME_STORED and o.subframe_seed == 0
 
 
 K7 = (7, (0o171, 0o133))
@@ -94,20 +95,22 @@ def test_invalid_arguments(vit):
     o = vit.vit_opts_default()
     o.check_finite = 2
     _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
-    for sub, ov in ((-1, 2), (1, -1), (2, (1 << 24) + 1)):
+    for sub, ov, rule in ((-1, 2, 0), (1, -1, 0), (2, (1 << 24) + 1, 0), (8, 4, 2), (8, 4, -1)):
         o = vit.vit_opts_default()
-        o.subframe_words, o.subframe_overlap = sub, ov
+        o.subframe_bits, o.subframe_overlap, o.subframe_start = sub, ov, rule
         _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
 
 
 def test_too_many_subframes(vit):
-    # at most 64 subframes per block: a full frame of 100000 bits has 3334
-    # words of 30 stages (K=7)
+    # at most 64 subframes per block (one lane per chain)
     c = _code(vit)
     o = vit.vit_opts_default()
-    o.subframe_words = 1
+    o.subframe_bits = 1
     _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode_ex, c, FAKE, 100000, 0, 0, 0, FAKE, o)
-    o.subframe_words = 52  # 65 subframes
+    o.subframe_bits = 8  # 65 subframes of a 520-bit core
+    _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode_ex, c, FAKE, 100000, 520, 35, 0, FAKE, o)
+    o.subframe_bits = 1563  # 64 subframes of the full frame: accepted by the host checks
+    o.llr_type, o.metric_bits = vit.VIT_LLR_I8, 16  # ... and then refused for the metric width
     _expect(vit, vit.VIT_EUNSUPPORTED, vit.vit_decode_ex, c, FAKE, 100000, 0, 0, 0, FAKE, o)
 
 
@@ -125,8 +128,8 @@ def test_unsupported_arguments(vit):
     _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
     o.metric_bits = 0
     _expect(vit, U, vit.vit_decode_ex, c, FAKE, 1 << 16, 0, 0, 0, FAKE, o)
-    # subframe traceback has no 16-bit metric kernel
-    o.metric_bits, o.subframe_words = 16, 2
+    # the parallel traceback has no 16-bit metric kernel
+    o.metric_bits, o.subframe_bits = 16, 16
     _expect(vit, U, vit.vit_decode_ex, c, FAKE, 4096, 256, 35, 0, FAKE, o)
     for bad in (1, 8, 64, -16):
         o = vit.vit_opts_default()

@@ -14,10 +14,6 @@ pytestmark = pytest.mark.gpu
 NCPU = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
-def word_stages(k):
-    return (k - 1) * (32 // (k - 1))
-
-
 def random_case(rng):
     k = int(rng.integers(3, 10))
     beta = int(rng.integers(2, 5))
@@ -28,8 +24,11 @@ def random_case(rng):
     v1 = None if rng.random() < 0.5 else int(rng.integers(0, v + 1))
     term = bool(rng.random() < 0.7)
     kind = ("f32", "i8", "hard")[int(rng.integers(0, 3))]
-    F, W = (0, 2) if rng.random() < 0.6 else (int(rng.integers(1, 5)), int(rng.integers(0, 4)))
-    return k, gens, n, L, v, v1, term, kind, F, W
+    sub = (0, 0, 0, 0) if rng.random() < 0.6 else (int(rng.integers(1, 65)), int(rng.integers(0, 50)),
+                                                     int(rng.integers(0, 2)), int(rng.integers(0, 1 << 62)))
+    if sub[0]:  # at most 64 subframes per block
+        sub = (max(sub[0], -(-(n if L == 0 else L) // 64)),) + sub[1:]
+    return k, gens, n, L, v, v1, term, kind, sub
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +46,7 @@ def test_random_cases(dev, seed):
     rng = np.random.default_rng(1000 + seed)
     ran = 0
     for case in range(40):
-        k, gens, n, L, v, v1, term, kind, F, W = random_case(rng)
+        k, gens, n, L, v, v1, term, kind, (f0, w, rule, sseed) = random_case(rng)
         N = n + (k - 1 if term else 0)
         llr = synth.awgn_llr(synth.encode(k, gens, synth.info_bits(n, rng), term), float(rng.uniform(0.0, 4.0)),
                              len(gens), rng)
@@ -61,10 +60,11 @@ def test_random_cases(dev, seed):
             x = llr
             ol = llr
         print(f"[gpu] seed={seed} case={case} k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} "
-              f"term={term} {kind} F={F} W={W}", flush=True)
+              f"term={term} {kind} f0={f0} w={w} rule={rule} seed={sseed}", flush=True)
         try:
             got = vit.decode(vit.make_code(k, gens), torch.from_numpy(np.ascontiguousarray(x)).cuda(), n, L, v,
-                             v1=v1, terminated=term, subframe_words=F, subframe_overlap=W)
+                             v1=v1, terminated=term, subframe_bits=f0, subframe_overlap=w, subframe_start=rule,
+                             subframe_seed=sseed)
             torch.cuda.synchronize()
         except vit.VitError as err:
             # only shapes the device cannot hold may be refused
@@ -76,8 +76,8 @@ def test_random_cases(dev, seed):
         if L == 0:
             Lb, e1, e2 = n, 0, k - 1 if term else 0
         c = vref.make_code(k, list(gens))
-        if F > 0:
-            want = vref.decode_blocked_split(c, ol, n, Lb, e1, e2, word_stages(k), F, W, term, nthreads=NCPU)
+        if f0 > 0:
+            want = vref.decode_blocked_pt(c, ol, n, Lb, e1, e2, f0, w, rule, sseed, term, nthreads=NCPU)
         else:
             want = vref.decode_blocked(c, ol, n, Lb, e1, e2, term, nthreads=NCPU)
         want = synth.pack_bits(want)

@@ -344,104 +344,3 @@ def test_int16_modulo_metrics_decide_like_exact_integers(k, gens, log2_stages, t
     assert (m_mod - m_exact) % (1 << 16) == 0
 
 
-# --------------------------------------------------------------------------- subframe traceback, Sec. IV-D
-
-def _chains(cs, e, k, G, F, W):
-    """Subframe chains of a block, recomputed from the definition: words of G
-    stages counted from the block end, subframe c = words [cF, (c+1)F), its
-    chain starting max(cF - W, 0) words below the end.  Yields (x, lo, hi):
-    the chain starts after stage x - 1 and gives the bits [lo, hi)."""
-    M = -(-(e - cs) // G)
-    C = -(-M // F)
-    for c in range(C):
-        x = e - max(c * F - W, 0) * G
-        hi = e if c == 0 else e - c * F * G - (k - 1)
-        lo = e - (c + 1) * F * G - (k - 1)
-        yield x, lo, hi
-
-
-@pytest.mark.parametrize("k,gens", [(3, (0o7, 0o5)), (4, (0o17, 0o13)), (5, (0o23, 0o35)),
-                                    (4, (0o13, 0o15, 0o17, 0o11))])
-@pytest.mark.parametrize("terminated", [True, False])
-def test_split_equals_bruteforce_per_subframe(k, gens, terminated):
-    # Each subframe's bits are the ML sequence of the stages its chain saw: a
-    # chain starting at the block end gives the ML bits of the block window
-    # [s, e) (end state known only at the end of a terminated stream); any
-    # other gives those of [s, x) with a free end (it starts from the best
-    # state after stage x-1).  Integer LLRs give ties, which must break as in
-    # the full-frame case.
-    c = _code(k, gens)
-    beta = len(gens)
-    rng = np.random.default_rng(300 + k)
-    seen = 0
-    for (n, L, v1, v2, G, F, W) in [(17, 8, 2, 3, 2, 2, 1), (13, 13, 0, 0, 2, 1, 0), (16, 6, 4, 2, 1, 2, 2),
-                                    (12, 12, 0, 4, 3, 1, 1), (11, 5, 1, 5, 2, 1, 0), (10, 10, 3, 3, 4, 9, 0),
-                                    (14, 14, 0, 2, 1, 3, 4)]:
-        N = n + (k - 1 if terminated else 0)
-        llr = synth.integer_llr(N * beta, -2, 2, rng)
-        want = np.zeros(n, dtype=np.uint8)
-        for (cs, ce, s, e) in _geometry(n, N, L, v1, v2):
-            if (k - 1) + (e - s) > 22:
-                pytest.skip("window too long for exhaustive search")
-            for (x, lo, hi) in _chains(cs, e, k, G, F, W):
-                a, b = max(lo, cs), min(hi, ce)
-                if a >= b:
-                    continue
-                end_zero = terminated and x == N
-                bf, _ = vref.bruteforce_window(c, llr.astype(np.float64), s, x, start_known=(s == 0),
-                                               end_zero=end_zero if x == e else False)
-                want[a:b] = bf[a - s:b - s]
-                seen += x < e
-        for dt in (np.float32, np.int8):
-            got = vref.decode_blocked_split(c, llr.astype(dt), n, L, v1, v2, G, F, W, terminated)
-            np.testing.assert_array_equal(got, want, err_msg=f"n={n} L={L} v1={v1} v2={v2} G={G} F={F} W={W} {dt}")
-    assert seen >= 8
-
-
-@pytest.mark.parametrize("name", list(synth.CODES))
-def test_split_noiseless_recovery(name):
-    # A free-end ML path over a noiseless window cannot leave the transmitted
-    # path (the first diverging branch always costs, every generator having its
-    # first tap set), so with v1 >= D (as for the plain blocked decoder) every
-    # bit of every subframe is exact, for any split.
-    k, gens = synth.CODES[name]
-    c = _code(k, gens)
-    D = _longest_zero_output_run(k, gens)
-    bits = synth.info_bits(1200, np.random.default_rng(12))
-    for terminated in (True, False):
-        llr = synth.noiseless_llr(vref.encode(c, bits, terminated))
-        for (L, G, F, W) in [(64, 30, 1, 0), (200, 7, 3, 3), (1200, 32, 2, 2), (5, 1, 1, 0), (300, 30, 1, 1)]:
-            got = vref.decode_blocked_split(c, llr, bits.size, L, D, 0, G, F, W, terminated)
-            np.testing.assert_array_equal(got, bits, err_msg=f"L={L} G={G} F={F} W={W}")
-
-
-def test_split_one_subframe_is_the_plain_blocked_decoder():
-    # with F >= M every block has one subframe, traced from the block end
-    k, gens = synth.CODES["k7r12"]
-    c = _code(k, gens)
-    bits, llr = synth.make_stream("k7r12", 5000, 1.5, seed=8)
-    want = vref.decode_blocked(c, llr, bits.size, 128, 20, 20, True)
-    for (G, F, W) in [(30, 6, 0), (30, 6, 3), (1000, 1, 0)]:
-        got = vref.decode_blocked_split(c, llr, bits.size, 128, 20, 20, G, F, W, True)
-        np.testing.assert_array_equal(got, want)
-
-
-def test_split_error_rate_falls_with_the_inner_overlap():
-    # Each lower subframe's start is a guess that the inner overlap corrects:
-    # with no overlap it costs errors, with two words the split decoder is as
-    # good as the plain one; shorter subframes (more guesses) cost more
-    # (Sec. IV-D and the parallel-traceback BER table).
-    k, gens = synth.CODES["k7r12"]
-    c = _code(k, gens)
-    bits, llr = synth.make_stream("k7r12", 200000, 2.0, seed=9)
-    plain = int((vref.decode_blocked(c, llr, bits.size, 256, 20, 20, True, nthreads=4) != bits).sum())
-
-    def errs(F, W):
-        return int((vref.decode_blocked_split(c, llr, bits.size, 256, 20, 20, 30, F, W, True, nthreads=4)
-                    != bits).sum())
-
-    e10, e11, e12, e40 = errs(1, 0), errs(1, 1), errs(1, 2), errs(4, 0)
-    assert e10 > 1.5 * plain + 20
-    assert e10 > e40 > plain
-    assert e11 > plain
-    assert e12 <= 1.02 * plain + 5
