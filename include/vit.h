@@ -297,17 +297,29 @@ typedef struct {
 int vit_plan_get_tuning(const vit_plan *plan, vit_tuning_entry *entries, int32_t max, int32_t *count);
 int vit_plan_set_tuning(vit_plan *plan, const vit_tuning_entry *entries, int32_t count);
 
-/* Autotune: for each code, time the batch's frames of that code with every
- * candidate shape (L in {64, 128, 256, 512, 1024}, v = 5k for k <= 7 and 8(k-1)
- * above, v1 = floor(v/2),
- * 1 or 2 waves per workgroup) and keep the fastest in the plan, keyed by
- * (code, llr_type, frame-length bucket).  chosen (may be NULL) receives one
- * vit_tuning per code.  Same buffers and errors as vit_decode_batch; the
- * output buffer holds the last candidate's result afterwards. */
+/* Autotune: for each code, decode the batch's frames of that code once with
+ * a reference shape whose overlap lies far beyond the trellis's convergence
+ * depth (L = 512, v1 = v2 = 128; Sec. III: the right overlap decides how
+ * close a block's decisions come to full-frame ML), then with every
+ * candidate shape: L in {64, 128, 256, 512, 1024}, v in {5k, 6k, 7k, 8(k-1),
+ * 10(k-1)} with v1 = floor(v/2), 1 or 2 waves per workgroup.  A candidate
+ * whose decoded bits differ from the reference's in more than the plan's
+ * tolerance (vit_plan_set_tune_tolerance; default 8e-4 of the code's bits)
+ * is rejected; the fastest of the others (3 timed runs each) is kept in the
+ * plan, keyed by (code, llr_type, frame-length bucket).  If none qualifies,
+ * the reference shape is kept.  chosen (may be NULL) receives one vit_tuning
+ * per code.  Same buffers and errors as vit_decode_batch (plus a host copy
+ * of the output buffer per candidate); the output buffer holds the last
+ * candidate's result afterwards. */
 int vit_plan_autotune(vit_plan *plan, const vit_code *codes, int32_t ncodes, const vit_frame *frames,
                       int32_t nframes, const void *llr, int64_t llr_count, int32_t llr_type, uint8_t *out,
                       int64_t out_bytes, void *workspace, size_t workspace_bytes, void *stream,
                       vit_tuning *chosen);
+
+/* The autotuner's accuracy bound: the largest fraction, in [0, 1], of a
+ * code's decoded bits in which an accepted shape may differ from the
+ * reference decode.  VIT_EINVAL outside [0, 1] (or NaN). */
+int vit_plan_set_tune_tolerance(vit_plan *plan, double max_diff_fraction);
 
 /* ---------------------------------------------------------------- serving
  * A request loop with continuous batching.  Requests are frames whose LLRs

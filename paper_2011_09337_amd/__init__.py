@@ -9,6 +9,7 @@ from . import _lib
 from ._lib import (FRAME_DTYPE, codes_array, frames_array, tunings_array, vit_batch_workspace_size, vit_decode_batch,
                    vit_decode_batch_static,
                    vit_plan_autotune, vit_plan_create, vit_plan_destroy, vit_plan_get_tuning, vit_plan_set_tuning,
+                   vit_plan_set_tune_tolerance,
                    vit_tuning_entry)
 from ._lib import (VIT_EBUSY, VIT_ETIMEDOUT, vit_server_config, vit_server_create, vit_server_destroy, vit_server_drain,
                    vit_server_poll, vit_server_stats, vit_server_submit, vit_server_submit_paced,
@@ -123,12 +124,14 @@ class Batch:
     The workspace is a torch uint8 tensor sized by vit_batch_workspace_size
     for the largest frame list seen."""
 
-    def __init__(self, device="cuda", metric_bits=0):
+    def __init__(self, device="cuda", metric_bits=0, tune_tolerance=None):
         self.plan = vit_plan_create()
         self.device = device
         self.ws = None
         if metric_bits:
             _lib.vit_plan_set_metric_bits(self.plan, metric_bits)
+        if tune_tolerance is not None:
+            _lib.vit_plan_set_tune_tolerance(self.plan, tune_tolerance)
 
     def close(self):
         if self.plan is not None:

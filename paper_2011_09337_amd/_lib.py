@@ -122,6 +122,8 @@ lib.vit_plan_create.argtypes = [C.POINTER(C.c_void_p)]
 lib.vit_plan_create.restype = C.c_int
 lib.vit_plan_set_metric_bits.argtypes = [C.c_void_p, C.c_int32]
 lib.vit_plan_set_metric_bits.restype = C.c_int
+lib.vit_plan_set_tune_tolerance.argtypes = [C.c_void_p, C.c_double]
+lib.vit_plan_set_tune_tolerance.restype = C.c_int
 lib.vit_plan_destroy.argtypes = [C.c_void_p]
 lib.vit_plan_destroy.restype = None
 lib.vit_batch_workspace_size.argtypes = [_PC, C.c_int32, _PF, C.c_int32, _PT, C.POINTER(C.c_size_t)]
@@ -259,6 +261,10 @@ def vit_plan_create():
 
 def vit_plan_set_metric_bits(plan, bits):
     return _check(lib.vit_plan_set_metric_bits(plan, int(bits)))
+
+
+def vit_plan_set_tune_tolerance(plan, max_diff_fraction):
+    return _check(lib.vit_plan_set_tune_tolerance(plan, float(max_diff_fraction)))
 
 
 def vit_plan_destroy(plan):

@@ -138,6 +138,7 @@ struct vit_server {
   vit::serve::Iteration iters[kInflight];  // reused, so their buffers keep their capacity
   std::deque<int> inflight;                // slots of the iterations on the device, oldest first
   int next_slot = 0;
+  int64_t admitted_seen = 0;               // core admissions already moved from `waiting` to `on_device`
   std::thread engine;
 };
 
@@ -225,11 +226,28 @@ void fail_locked(vit_server *s, int status, const std::string &msg) {
   }
 }
 
+// Move the core's new admissions from the queued count to the on-device
+// count (engine thread).
+void sync_admitted(vit_server *s) {
+  const int64_t total = s->core->admitted_total();
+  if (total == s->admitted_seen) return;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->waiting -= total - s->admitted_seen;
+  s->on_device += total - s->admitted_seen;
+  s->admitted_seen = total;
+}
+
 // Report finished (or failed) frames; `admitted` of them were on the device,
-// the rest were still waiting.
+// the rest were still waiting.  The counts drop first, so that an allocation
+// failure while the completions are queued loses completions, never the
+// server's accounting (drain still returns).
 void finish_frames(vit_server *s, const std::vector<vit::serve::Frame> &frames, int st, int64_t now,
                    int64_t admitted) {
   std::lock_guard<std::mutex> lk(s->mu);
+  s->on_device -= admitted;
+  s->waiting -= (int64_t)frames.size() - admitted;
+  s->last_done = now;
+  s->idle_cv.notify_all();
   for (const auto &f : frames) {
     s->done.push_back({f.tag, st, 0, f.arrival_ns, now});
     if (st == VIT_OK) {
@@ -251,11 +269,7 @@ void finish_frames(vit_server *s, const std::vector<vit::serve::Frame> &frames, 
     } else {
       ++s->failed_frames;
     }
-    s->last_done = now;
   }
-  s->on_device -= admitted;
-  s->waiting -= (int64_t)frames.size() - admitted;
-  s->idle_cv.notify_all();
 }
 
 void engine_loop(vit_server *s) {
@@ -272,6 +286,7 @@ void engine_loop(vit_server *s) {
     }
     for (const auto &f : arrived) s->core->submit(f);
     arrived.clear();
+    sync_admitted(s);  // also catches up after an exception inside next_iteration
     if (s->max_wait_ns > 0 && !failed) {
       // queue timeouts, before anything more is admitted
       const int64_t now = mono_ns();
@@ -291,11 +306,13 @@ void engine_loop(vit_server *s) {
         fail_locked(s, st, std::string("iteration failed: ") + hipGetErrorString(q));
         failed = true;
       }
+      // leave the in-flight list before reporting, so that a failure while
+      // reporting cannot report the iteration twice
       vit::serve::Iteration &it = s->iters[s->inflight.front()];
-      finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
-      s->core->retire(it);
       s->inflight.pop_front();
+      s->core->retire(it);
       progressed = true;
+      finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
     }
     if (failed && s->inflight.empty() && s->core->has_work()) {
       // after a device error nothing more is launched: queued and admitted
@@ -319,12 +336,12 @@ void engine_loop(vit_server *s) {
       vit::serve::Iteration &it = s->iters[slot];
       StagingSink sink;
       sink.wi = (vit::WorkItem *)((uint8_t *)s->staging[slot] + kHeaderBytes);
-      if (s->core->next_iteration(&it, sink)) {
+      const bool any = s->core->next_iteration(&it, sink);
+      sync_admitted(s);
+      if (any) {
         s->next_slot = (slot + 1) % kInflight;
         {
           std::lock_guard<std::mutex> lk(s->mu);
-          s->waiting -= it.admitted;
-          s->on_device += it.admitted;
           s->peak_arena = std::max(s->peak_arena, s->core->arena_in_use());
           s->peak_frames = std::max(s->peak_frames, s->core->frames_on_device());
           ++s->iterations;
@@ -339,9 +356,9 @@ void engine_loop(vit_server *s) {
             fail_locked(s, st, msg);
           }
           // the iteration's event was not recorded: its frames fail now
-          finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
-          s->core->retire(it);
           s->inflight.pop_back();
+          s->core->retire(it);
+          finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
         }
         continue;
       }
@@ -493,6 +510,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   try {
     vit::alloc_checkpoint();
     s->core = new vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames, cfg->max_items);
+    s->core->checkpoint = &vit::alloc_checkpoint;
   } catch (const std::bad_alloc &) {
     return bail(api_fail(VIT_ENOMEM, "core allocation failed"));
   }

@@ -159,6 +159,13 @@ class Core {
   size_t pending() const { return pending_.size(); }
   size_t active() const { return active_.size(); }
   int64_t frames_on_device() const { return on_device_; }
+  // Frames admitted since the core was made (monotonic): the engine derives
+  // its queued / on-device counts from it, so an exception part-way through
+  // next_iteration leaves them consistent.
+  int64_t admitted_total() const { return admitted_total_; }
+  // Called by next_iteration after admission, before scheduling (the
+  // server's host-allocation checkpoint, so tests can fail it there).
+  void (*checkpoint)() = nullptr;
   int64_t arena_in_use() const { return ring_.in_use(); }
   bool has_work() const { return !pending_.empty() || !active_.empty(); }
 
@@ -184,14 +191,20 @@ class Core {
       active_.push_back(f);
       pending_.pop_front();
       ++on_device_;
+      ++admitted_total_;
       ++it->admitted;
     }
+    if (checkpoint) checkpoint();
     // Blocks per frame, in two passes over the active frames in admission
     // order: first each frame gets an equal share of the iteration (at least
     // one block), so short frames that joined late finish without waiting
     // behind long ones; then what is left goes to the oldest frames.
     const size_t na = active_.size();
     take_.assign(na, 0);
+    // room for every frame to finish, so that the compaction below cannot
+    // throw half-way
+    it->egress.reserve(na);
+    it->finishing.reserve(na);
     int64_t room = max_items_;
     const int64_t share = na ? std::max<int64_t>(1, room / (int64_t)na) : 0;
     for (int pass = 0; pass < 2 && room > 0; ++pass) {
@@ -300,6 +313,7 @@ class Core {
   std::deque<Frame> pending_;
   std::deque<Frame> active_;
   int64_t on_device_ = 0;
+  int64_t admitted_total_ = 0;
 };
 
 }  // namespace serve

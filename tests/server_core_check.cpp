@@ -295,6 +295,57 @@ int main(int argc, char **argv) {
   core.fail_all([&](const Frame &, bool) { ++dropped; });
   core.retire(it);
   CHECK(!core.has_work() && core.frames_on_device() == 0 && core.arena_in_use() == 0, "fail_all left work");
+  // an exception at the checkpoint after admission: the admitted frames stay
+  // counted (admitted_total, frames_on_device) and fail_all reports each of
+  // them once, as admitted, and each queued one once, as queued
+  {
+    Core x(shapes, elem, arena, max_frames, max_items);
+    struct Boom {};
+    static bool armed;
+    armed = true;
+    x.checkpoint = [] {
+      if (armed) {
+        armed = false;
+        throw Boom();
+      }
+    };
+    int64_t sent = 0;
+    for (int j = 0; j < 3 * max_frames; ++j) {
+      Frame f;
+      f.tag = 5000 + (uint64_t)j;
+      f.code = j % (int)shapes.size();
+      f.terminated = 1;
+      f.n = 24;
+      f.N = f.n + shapes[f.code].k - 1;
+      f.llr_bytes = f.N * shapes[f.code].beta * elem;
+      f.llr_src = 0;
+      f.out_dst = 0;
+      f.arrival_ns = 0;
+      if (!x.fits_ever(f)) continue;
+      x.submit(f);
+      ++sent;
+    }
+    Iteration it;
+    VectorSink sink;
+    bool threw = false;
+    try {
+      x.next_iteration(&it, sink);
+    } catch (const Boom &) {
+      threw = true;
+    }
+    CHECK(threw && x.admitted_total() > 0 && x.admitted_total() == x.frames_on_device(),
+          "admissions before the exception: %lld counted, %lld on device", (long long)x.admitted_total(),
+          (long long)x.frames_on_device());
+    int64_t adm = 0, queued = 0;
+    std::set<uint64_t> seen;
+    x.fail_all([&](const Frame &f, bool a) {
+      CHECK(seen.insert(f.tag).second, "frame %llu reported twice", (unsigned long long)f.tag);
+      (a ? adm : queued) += 1;
+    });
+    CHECK(adm == x.admitted_total() && adm + queued == sent, "fail_all: %lld admitted + %lld queued of %lld",
+          (long long)adm, (long long)queued, (long long)sent);
+    CHECK(!x.has_work() && x.frames_on_device() == 0 && x.arena_in_use() == 0, "work left after the exception");
+  }
   printf("OK seed %llu: %lld frames, arena %lld, slots %d, items/iter %d, L %lld/%lld/%lld\n",
          (unsigned long long)seed, (long long)finished, (long long)arena, max_frames, max_items,
          (long long)shapes[0].L, (long long)shapes[1].L, (long long)shapes[2].L);

@@ -101,6 +101,21 @@ def test_invalid_arguments(vit):
         _expect(vit, E, vit.vit_decode_ex, c, FAKE, 100, 8, 4, 0, FAKE, o)
 
 
+def test_tune_tolerance_validated(vit):
+    b = vit.Batch.__new__(vit.Batch)  # a plan without a device workspace
+    b.plan = vit.vit_plan_create()
+    try:
+        for bad in (-1e-9, 1.5, float("nan"), float("inf")):
+            with pytest.raises(vit.VitError) as ei:
+                vit.vit_plan_set_tune_tolerance(b.plan, bad)
+            assert ei.value.status == vit.VIT_EINVAL
+        for ok in (0.0, 6e-4, 1.0):
+            vit.vit_plan_set_tune_tolerance(b.plan, ok)
+    finally:
+        vit.vit_plan_destroy(b.plan)
+        b.plan = None
+
+
 def test_too_many_subframes(vit):
     # at most 64 subframes per block (one lane per chain)
     c = _code(vit)

@@ -265,6 +265,33 @@ def test_forced_allocation_failures(dev):
         np.testing.assert_array_equal(h[oo:oo + (fr[2] + 7) // 8], expected_alone(torch, vit, fr, TUNE))
 
 
+def test_engine_allocation_failure_fails_the_server(dev):
+    # a host allocation failure inside the engine's scheduling step (after
+    # admission): the server fails with VIT_ENOMEM, every frame is reported
+    # exactly once, and drain returns the failure instead of waiting forever
+    torch, vit = dev
+    rng = np.random.default_rng(17)
+    frames = make_frames(rng, 30, 40, 600, True)
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    lib = vit._lib.lib
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=64,
+                     max_items=256)
+    try:
+        assert lib.vit_debug_fail_allocations(1) == vit.VIT_OK
+        st, acc = srv.submit(requests(vit, host, frames, offs, list(range(len(frames)))))
+        assert st == vit.VIT_OK and acc == len(frames)
+        with pytest.raises(vit.VitError) as ei:
+            srv.drain(timeout_ms=30000)
+        assert ei.value.status == vit.VIT_ENOMEM
+        comps = srv.poll()
+    finally:
+        assert lib.vit_debug_fail_allocations(0) == vit.VIT_OK
+        srv.close()
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames)))
+    assert (comps["status"] == vit.VIT_ENOMEM).all()
+
+
 def test_queue_timeout(dev):
     # requests still queued max_wait_ms after their arrival complete with
     # VIT_ETIMEDOUT and are not decoded (their output bytes stay as they
