@@ -23,6 +23,7 @@ from oracle import vref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 M64 = 2 ** 64 - 1
+NTHREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def _code(k, gens):
@@ -221,3 +222,41 @@ def test_pt_rejects_bad_arguments():
         vref.decode_blocked_pt(c, llr, 10, 4, 1, 1, 2, -1)
     with pytest.raises(ValueError):
         vref.decode_blocked_pt(c, llr, 10, 4, 1, 1, 2, 1, start_rule=2)
+
+
+def test_pt_random_start_reproduces_the_papers_ber_gaps():
+    # The paper's BER-gap table of the parallel traceback (Table III: Eb/N0
+    # gap at BER 1e-4 to the theoretical curve, K=7 r1/2, f = 300) against
+    # this decoder with random chain starts (frames of 300 bits, v1 = 20,
+    # right overlap v2 = w), the gap taken to the full-frame ML decode of the
+    # same streams.  Two cells, 2^22 bits per Eb/N0 point (about 400 errors at
+    # BER 1e-4, so about +-0.04 dB of estimate noise).
+    k, gens = synth.CODES["k7r12"]
+    c = _code(k, gens)
+    n = 1 << 22
+    grid = [3.0, 3.5, 4.0, 4.5, 5.0]
+    cells = {(30, 24): 1.09, (40, 8): 0.43}
+    errs = {"ml": []}
+    for key in cells:
+        errs[key] = []
+    for e in grid:
+        bits, llr = synth.make_stream("k7r12", n, e, seed=500 + int(e * 10))
+        errs["ml"].append(int((vref.decode_full(c, llr.astype(np.float64), n) != bits).sum()))
+        for (w, f0) in cells:
+            got = vref.decode_blocked_pt(c, llr, n, 300, 20, w, f0, w, vref.PT_RANDOM, 99, True,
+                                         nthreads=NTHREADS)
+            errs[(w, f0)].append(int((got != bits).sum()))
+
+    def at_1e4(es):
+        bers = [max(x, 0.5) / n for x in es]
+        for i in range(len(grid) - 1):
+            if bers[i] >= 1e-4 > bers[i + 1]:
+                y0, y1 = np.log(bers[i]), np.log(bers[i + 1])
+                return grid[i] + (np.log(1e-4) - y0) * (grid[i + 1] - grid[i]) / (y1 - y0)
+        raise AssertionError(f"BER 1e-4 not bracketed: {es}")
+
+    ml = at_1e4(errs["ml"])
+    for key, paper in cells.items():
+        gap = at_1e4(errs[key]) - ml
+        print(f"v2={key[0]} f0={key[1]}: gap {gap:.3f} dB (paper {paper})")
+        assert abs(gap - paper) < 0.12, (key, gap, paper)
