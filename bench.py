@@ -342,13 +342,17 @@ def bench_serving(vit, torch, args, tunes):
     frames, host = serving_pool(vit, torch, args.serve_pool)
     codes = [vit.make_code(*synth.CODES[c]) for c in BATCH_CODES]
     srv = vit.Server(codes, host, tune=tunes, llr_type=vit.VIT_LLR_I8, arena_bytes=args.serve_arena_mb << 20,
-                     max_frames=16384, max_items=1 << 16, max_pending=1 << 24)
+                     max_frames=1 << 16, max_items=1 << 16, max_pending=1 << 24)
     base = host.data_ptr()
     P = len(frames)
     pool = np.zeros(P, dtype=vit.REQUEST_DTYPE)
     for i, (cid, n, lo, oo) in enumerate(frames):
         pool[i] = (cid, 1, n, base + lo, base + oo, i, 0)
     mean_bits = float(np.mean(pool["n"]))
+    # algorithmic work of a mean pool frame under the shapes (the arrivals
+    # cycle through the pool, so a point's completed frames carry about this
+    # much each): 4 operations per state per trellis stage
+    mean_work = 4.0 * batch_stages([(cid, 1, n, 0, 0) for cid, n, _, _ in frames], tunes) / P
 
     def requests(first, count, arrivals=None):
         idx = (first + np.arange(count)) % P
@@ -371,7 +375,7 @@ def bench_serving(vit, torch, args, tunes):
         srv.stats(reset=True)
         cap = None
         for rep in range(3):
-            nreq = P * (2 if rep == 0 else 4)
+            nreq = P * (4 if rep == 0 else 16)  # a backlog long enough for the pipeline to fill
             t0 = time.monotonic_ns()
             submit_all(requests(0, nreq))
             srv.drain(timeout_ms=120000)
@@ -436,11 +440,23 @@ def bench_serving(vit, torch, args, tunes):
             points.append({
                 "load": load, "offered_fps": round(rate, 1), "frames": st["completed"],
                 "mbps": round(st["bits_completed"] / span / 1e6, 2),
+                "alu_frac": round(st["completed"] * mean_work / span / 1e12 / ALU_PEAK_TOPS, 4),
                 "p50_ms": round(st["p50_ns"] * 1e-6, 3), "p99_ms": round(st["p99_ns"] * 1e-6, 3),
                 "max_ms": round(st["max_ns"] * 1e-6, 3), "iterations": st["iterations"],
                 "mean_items_per_iteration": round(st["items_launched"] / max(1, st["iterations"]), 1),
                 "peak_frames_on_device": st["peak_frames_on_device"],
-                "peak_arena_MiB": round(st["peak_arena_bytes"] / 2 ** 20, 2)})
+                "peak_arena_MiB": round(st["peak_arena_bytes"] / 2 ** 20, 2),
+                # where the time goes (device events per iteration, host clocks per frame)
+                "ingest_busy": round(st["iter_ingest_ns"] * 1e-9 / span, 3),
+                "decode_busy": round(st["iter_decode_ns"] * 1e-9 / span, 3),
+                "mean_ingest_ms": round(st["iter_ingest_ns"] * 1e-6 / max(1, st["iterations"]), 4),
+                "mean_decode_ms": round(st["iter_decode_ns"] * 1e-6 / max(1, st["iterations"]), 4),
+                "max_iteration_ms": round(st["iter_max_ns"] * 1e-6, 3),
+                "engine_host_busy": round(st["engine_host_ns"] * 1e-9 / span, 3),
+                "mean_admit_wait_ms": round(st["admit_wait_ns"] * 1e-6 / max(1, st["completed"]), 4),
+                "max_admit_wait_ms": round(st["admit_wait_max_ns"] * 1e-6, 3),
+                "mean_submit_lag_ms": round(st["submit_lag_ns"] * 1e-6 / max(1, st["submit_lag_count"]), 4),
+                "max_submit_lag_ms": round(st["submit_lag_max_ns"] * 1e-6, 3)})
             print(f"serving: load {load:g} done ({st['completed']} frames, p99 {points[-1]['p99_ms']} ms)",
                   file=sys.stderr, flush=True)
     finally:
@@ -453,6 +469,7 @@ def bench_serving(vit, torch, args, tunes):
                     f"(vit_server_submit_paced); latency from arrival to completion seen by the host",
         "capacity_fps": round(cap, 1),
         "capacity_mbps": round(cap * mean_bits / 1e6, 2),
+        "capacity_alu_frac": round(cap * mean_work / 1e12 / ALU_PEAK_TOPS, 4),
         "arena_MiB": args.serve_arena_mb,
         "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
         "points": points,

@@ -328,10 +328,12 @@ int vit_plan_set_tune_tolerance(vit_plan *plan, double max_diff_fraction);
  * allow, and runs iterations of at most max_items blocks (the independent
  * windows of Sec. III) taken from the admitted frames in arrival order.  A
  * long frame spreads over several iterations; frames that arrive while the
- * device is busy join the next one, and two iterations are in flight at once.
- * Each iteration gathers its new frames' LLRs into the arena, decodes its
- * blocks with the persistent batch kernels and scatters finished frames'
- * decoded bytes back into the host region.  A frame's decoded bits are
+ * device is busy join the next one, and two iterations are in flight at
+ * once.  Each iteration gathers its new frames' LLRs into the arena (on a
+ * stream of the server's own, so that it overlaps the decode of the
+ * iteration before), decodes its blocks with the persistent batch kernels
+ * and scatters finished frames' decoded bytes back into the host region (on
+ * the configured stream).  A frame's decoded bits are
  * identical to decoding it alone with vit_decode_ex and its code's
  * (L, v, v1); only the block is the unit of scheduling, and a block's path
  * metrics stay on chip.  Latency runs from the request's arrival time to the
@@ -384,6 +386,21 @@ typedef struct {
   int64_t pending, frames_on_device, peak_frames_on_device, peak_arena_bytes;
   int64_t first_arrival_ns, last_done_ns;
   int64_t p50_ns, p99_ns, max_ns;   /* latency of completed frames */
+  /* Where the time goes.  Device time per retired iteration, from events:
+   * its ingest (work-list copy and LLR gather on the server's stream) and its
+   * decode (batch kernels and scatter on the configured stream, from the
+   * moment that stream starts it); summed, and the longest iteration from
+   * ingest start to completion. */
+  int64_t iter_ingest_ns, iter_decode_ns, iter_max_ns;
+  /* Admission wait (admission time - arrival), summed and largest. */
+  int64_t admit_wait_ns, admit_wait_max_ns;
+  /* Hand-over lag of requests that carry an arrival time (the time they
+   * reach vit_server_submit - arrival_ns: for vit_server_submit_paced, how
+   * late the replay runs), summed over submit_lag_count requests, and the
+   * largest. */
+  int64_t submit_lag_ns, submit_lag_max_ns, submit_lag_count;
+  /* Host time the engine thread spent scheduling and launching iterations. */
+  int64_t engine_host_ns;
 } vit_serve_stats;
 
 /* Device workspace bytes for a configuration (two iterations' work lists). */

@@ -86,7 +86,8 @@ class vit_serve_stats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in (
         "submitted", "completed", "failed", "bits_completed", "iterations", "items_launched", "pending",
         "frames_on_device", "peak_frames_on_device", "peak_arena_bytes", "first_arrival_ns", "last_done_ns",
-        "p50_ns", "p99_ns", "max_ns")]
+        "p50_ns", "p99_ns", "max_ns", "iter_ingest_ns", "iter_decode_ns", "iter_max_ns", "admit_wait_ns",
+        "admit_wait_max_ns", "submit_lag_ns", "submit_lag_max_ns", "submit_lag_count", "engine_host_ns")]
 
 
 class VitError(RuntimeError):

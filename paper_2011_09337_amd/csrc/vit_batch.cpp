@@ -36,7 +36,8 @@ struct vit_plan {
   bool have_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t copy_node = nullptr;
+  hipGraphNode_t copy_node = nullptr;                   // the header
+  hipGraphNode_t code_copy[vit::kMaxCodes] = {};         // each code's run of work items
   // per code: its kernel node, launch shape, arguments and current grid
   hipGraphNode_t knode[vit::kMaxCodes] = {};
   vit::BatchLaunch bl[vit::kMaxCodes] = {};
@@ -314,12 +315,28 @@ int ensure_staging(vit_plan *p, int slot, size_t bytes) {
   return VIT_OK;
 }
 
+// The bytes of code c's work items in the staging area and the workspace (a
+// code without items copies the header again, a copy of no bytes being no
+// graph node).
+struct CodeCopy {
+  void *dst;
+  const void *src;
+  size_t bytes;
+};
+CodeCopy code_copy_range(const int32_t *header, int c, void *workspace, const void *stg) {
+  const int64_t count = header[kMaxCodes + c];
+  if (count == 0) return {workspace, stg, kHeaderBytes};
+  const size_t off = kHeaderBytes + (size_t)header[2 * kMaxCodes + c] * sizeof(WorkItem);
+  return {(char *)workspace + off, (const char *)stg + off, (size_t)count * sizeof(WorkItem)};
+}
+
 void drop_graph(vit_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
   p->copy_node = nullptr;
+  for (auto &n : p->code_copy) n = nullptr;
   p->have_graph = false;
 }
 
@@ -466,17 +483,27 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
     }
     he = hipGraphCreate(&plan->graph, 0);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphCreate");
-    he = hipGraphAddMemcpyNode1D(&plan->copy_node, plan->graph, nullptr, 0, workspace, stg, need,
+    he = hipGraphAddMemcpyNode1D(&plan->copy_node, plan->graph, nullptr, 0, workspace, stg, kHeaderBytes,
                                  hipMemcpyHostToDevice);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddMemcpyNode1D");
     // one kernel node per code, run one after another, the code with the
     // most work per bit (states x rate) first: measured faster than running
-    // them side by side
+    // them side by side.  Each code's work items are copied by a node of
+    // their own, the copies chained in launch order, so that a kernel waits
+    // only for its own items and the later codes' copies run during the
+    // earlier kernels.
     int order[kMaxCodes];
     vit::batch_code_order(codes, ncodes, order);
-    hipGraphNode_t prev = plan->copy_node;
+    hipGraphNode_t prev = nullptr, prev_copy = plan->copy_node;
     for (int oi = 0; oi < ncodes; ++oi) {
       const int c = order[oi];
+      {
+        const CodeCopy cc = code_copy_range(header, c, workspace, stg);
+        he = hipGraphAddMemcpyNode1D(&plan->code_copy[c], plan->graph, &prev_copy, 1, cc.dst, cc.src, cc.bytes,
+                                     hipMemcpyHostToDevice);
+        if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddMemcpyNode1D");
+        prev_copy = plan->code_copy[c];
+      }
       vit::BatchArgs &args = plan->kargs[c];
       args.llr = llr;
       args.out = out;
@@ -496,7 +523,8 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
       kp.kernelParams = kargs;
       kp.extra = nullptr;
       hipGraphNode_t kn;
-      he = hipGraphAddKernelNode(&kn, plan->graph, &prev, 1, &kp);
+      hipGraphNode_t deps[2] = {plan->code_copy[c], prev};
+      he = hipGraphAddKernelNode(&kn, plan->graph, deps, prev ? 2 : 1, &kp);
       if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphAddKernelNode");
       plan->knode[c] = kn;
       prev = kn;
@@ -510,9 +538,15 @@ static int decode_batch_impl(vit_plan *plan, const vit_code *codes, int32_t ncod
     plan->key = key;
     plan->have_graph = true;
   } else {
-    he = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->copy_node, workspace, stg, need,
+    he = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->copy_node, workspace, stg, kHeaderBytes,
                                            hipMemcpyHostToDevice);
     if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphExecMemcpyNodeSetParams1D");
+    for (int c = 0; c < ncodes; ++c) {
+      const CodeCopy cc = code_copy_range(header, c, workspace, stg);
+      he = hipGraphExecMemcpyNodeSetParams1D(plan->exec, plan->code_copy[c], cc.dst, cc.src, cc.bytes,
+                                             hipMemcpyHostToDevice);
+      if (he != hipSuccess) return vit::api_fail_hip(he, "hipGraphExecMemcpyNodeSetParams1D");
+    }
     // the item counts change from call to call: resize the dispatcher-refilled grids
     for (int c = 0; c < ncodes; ++c) {
       const unsigned g = grid_for(c);

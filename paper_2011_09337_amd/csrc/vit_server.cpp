@@ -3,13 +3,15 @@
 // Requests (one frame each, LLRs in a pinned host region) are queued by
 // vit_server_submit.  An engine thread owned by the server runs iterations:
 // each admits queued frames while slots and device arena memory allow (the
-// scheduling lives in vit_server_core.h), then issues, on the server's
-// stream, one host-to-device copy of the iteration's work list, one gather of
-// the new frames' LLRs from the host region into the arena, one persistent
-// batch kernel per code over the iteration's blocks, one scatter of the
-// finished frames' decoded bytes into the host region, and an event.  Two
-// iterations are in flight at once, so requests that arrive while the device
-// is busy join the next iteration and their work overlaps the running one.
+// scheduling lives in vit_server_core.h), then issues, on the server's own
+// ingest stream, one host-to-device copy of the iteration's work list and one
+// gather of the new frames' LLRs from the host region into the arena (over
+// PCIe), and on the caller's stream, after the ingest, one persistent batch
+// kernel per code over the iteration's blocks, one scatter of the finished
+// frames' decoded bytes into the host region, and an event.  Two iterations
+// are in flight at once, so requests that arrive while the device is busy
+// join the next iteration, and an iteration's ingest runs while the one
+// before it decodes.
 // A frame completes when the host sees its last iteration's event; its
 // latency runs from its arrival time to that moment (CLOCK_MONOTONIC).
 #include <hip/hip_runtime.h>
@@ -38,6 +40,10 @@ using vit::api_fail;
 using vit::kHeaderBytes;
 using vit::kMaxCodes;
 
+// Iterations in flight: one decoding while the next ingests.  A third
+// measured no lower latency at low load and smaller, less efficient
+// iterations at high load (each iteration carries a fixed cost of about
+// 0.09 ms: kernel launches and the last blocks' tails).
 constexpr int kInflight = 2;
 constexpr int64_t kLatSample = 1 << 24;  // latency percentiles from at most this many samples
 
@@ -111,8 +117,12 @@ struct vit_server {
   int32_t max_frames = 0, max_items = 0, max_pending = 0;
   int64_t max_wait_ns = 0;  // queue timeout, 0 = none
 
-  void *staging[kInflight] = {nullptr, nullptr};
-  hipEvent_t ev[kInflight] = {nullptr, nullptr};
+  void *staging[kInflight] = {};
+  hipEvent_t ev[kInflight] = {};         // the iteration is complete (decode and scatter)
+  hipEvent_t ingested[kInflight] = {};   // its work list and LLRs are on the device
+  hipEvent_t t_ingest[kInflight] = {};   // its ingest starts (timing)
+  hipEvent_t t_decode[kInflight] = {};   // its decode starts (timing)
+  hipStream_t ingest = nullptr;          // the server's own stream for the ingest
 
   // Shared with the callers, under `mu`: the hand-off queue, completions,
   // counters.  The lock is never held while a work list is built or HIP is
@@ -127,6 +137,8 @@ struct vit_server {
   uint64_t lat_rng = 0x9e3779b97f4a7c15ull;
   int64_t submitted = 0, completed = 0, failed_frames = 0, bits_completed = 0, iterations = 0,
           items_launched = 0, peak_arena = 0, peak_frames = 0, first_arrival = 0, last_done = 0;
+  int64_t iter_ingest = 0, iter_decode = 0, iter_max = 0, admit_wait = 0, admit_wait_max = 0, submit_lag = 0,
+          submit_lag_max = 0, submit_lag_count = 0, engine_host = 0;
   int64_t waiting = 0;             // submitted, not yet admitted
   int64_t on_device = 0;           // admitted, not yet finished
   int status = VIT_OK;
@@ -191,11 +203,23 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     er[i] = {s->arena + it.egress[i].src, s->host_dev + it.egress[i].dst, it.egress[i].bytes, 0};
   const size_t used = items_end + (it.ingest.size() + it.egress.size()) * sizeof(vit::CopyRange);
 
-  hipError_t e = hipMemcpyAsync(wsd, stg, used, hipMemcpyHostToDevice, s->stream);
+  // ingest on the server's stream: it overlaps the decode of the iteration
+  // before (whose arena ranges and workspace slot it does not touch: slots
+  // are reused only after their iteration retired, and the ring allocator
+  // gives new frames free arena)
+  hipError_t e = hipEventRecord(s->t_ingest[slot], s->ingest);
+  if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
+  e = hipMemcpyAsync(wsd, stg, used, hipMemcpyHostToDevice, s->ingest);
   if (e != hipSuccess) return *msg = std::string("hipMemcpyAsync: ") + hipGetErrorString(e), VIT_EDEVICE;
   const vit::CopyRange *dcr = (const vit::CopyRange *)(wsd + items_end);
-  e = vit::launch_copy_list(dcr, (int32_t)it.ingest.size(), s->stream);
+  e = vit::launch_copy_list(dcr, (int32_t)it.ingest.size(), s->ingest);
   if (e != hipSuccess) return *msg = std::string("ingest: ") + hipGetErrorString(e), VIT_EDEVICE;
+  e = hipEventRecord(s->ingested[slot], s->ingest);
+  if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
+  e = hipStreamWaitEvent(s->stream, s->ingested[slot], 0);
+  if (e != hipSuccess) return *msg = std::string("hipStreamWaitEvent: ") + hipGetErrorString(e), VIT_EDEVICE;
+  e = hipEventRecord(s->t_decode[slot], s->stream);
+  if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
   for (int c = 0; c < s->ncodes; ++c) {
     if (!it.count[c]) continue;
     vit::BatchArgs a;
@@ -308,8 +332,20 @@ void engine_loop(vit_server *s) {
       }
       // leave the in-flight list before reporting, so that a failure while
       // reporting cannot report the iteration twice
-      vit::serve::Iteration &it = s->iters[s->inflight.front()];
+      const int slot = s->inflight.front();
+      vit::serve::Iteration &it = s->iters[slot];
       s->inflight.pop_front();
+      if (st == VIT_OK) {
+        float a = 0, b = 0, c = 0;
+        if (hipEventElapsedTime(&a, s->t_ingest[slot], s->ingested[slot]) == hipSuccess &&
+            hipEventElapsedTime(&b, s->t_decode[slot], s->ev[slot]) == hipSuccess &&
+            hipEventElapsedTime(&c, s->t_ingest[slot], s->ev[slot]) == hipSuccess) {
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->iter_ingest += (int64_t)(a * 1e6f);
+          s->iter_decode += (int64_t)(b * 1e6f);
+          s->iter_max = std::max(s->iter_max, (int64_t)(c * 1e6f));
+        }
+      }
       s->core->retire(it);
       progressed = true;
       finish_frames(s, it.finishing, st, mono_ns(), (int64_t)it.finishing.size());
@@ -331,17 +367,35 @@ void engine_loop(vit_server *s) {
       finish_frames(s, dropped, st, mono_ns(), admitted);
     }
     if (stop && s->inflight.empty()) break;
-    if (!failed && !stop && (int)s->inflight.size() < kInflight && s->core->has_work()) {
+    // Launch policy: a new iteration goes out when a slot is free and the
+    // newest iteration in flight has finished its ingest (it is decoding or
+    // waiting to decode).  Work that arrives during an ingest then joins the
+    // next iteration instead of a small one of its own: every iteration
+    // carries a fixed device cost (launches, the last blocks' tails), so
+    // fewer, larger iterations carry more at high load, while at low load the
+    // ingests are short and the wait is too.
+    bool slot_free = (int)s->inflight.size() < kInflight;
+    bool deferred = false;
+    if (slot_free && !s->inflight.empty() && s->core->has_work()) {
+      if (hipEventQuery(s->ingested[s->inflight.back()]) == hipErrorNotReady) {
+        slot_free = false;
+        deferred = true;
+      }
+    }
+    if (!failed && !stop && slot_free && s->core->has_work()) {
+      const int64_t t_host = mono_ns();
       const int slot = s->next_slot;
       vit::serve::Iteration &it = s->iters[slot];
       StagingSink sink;
       sink.wi = (vit::WorkItem *)((uint8_t *)s->staging[slot] + kHeaderBytes);
-      const bool any = s->core->next_iteration(&it, sink);
+      const bool any = s->core->next_iteration(&it, sink, mono_ns());
       sync_admitted(s);
       if (any) {
         s->next_slot = (slot + 1) % kInflight;
         {
           std::lock_guard<std::mutex> lk(s->mu);
+          s->admit_wait += it.admit_wait_sum;
+          s->admit_wait_max = std::max(s->admit_wait_max, it.admit_wait_max);
           s->peak_arena = std::max(s->peak_arena, s->core->arena_in_use());
           s->peak_frames = std::max(s->peak_frames, s->core->frames_on_device());
           ++s->iterations;
@@ -350,6 +404,10 @@ void engine_loop(vit_server *s) {
         s->inflight.push_back(slot);
         std::string msg;
         const int st = launch_iteration(s, it, slot, &msg);
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->engine_host += mono_ns() - t_host;
+        }
         if (st != VIT_OK) {
           {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -364,8 +422,14 @@ void engine_loop(vit_server *s) {
       }
     }
     if (progressed) continue;
-    // nothing to launch: wait for a submit, or poll the running iteration
+    // nothing to launch now: wait for a submit, or poll the running
+    // iterations (a deferred launch polls without waiting for submits, which
+    // cannot make it go out sooner)
     std::unique_lock<std::mutex> lk(s->mu);
+    if (deferred) {
+      if (!s->stop) s->cv.wait_for(lk, std::chrono::microseconds(10), [&] { return s->stop; });
+      continue;
+    }
     if (!s->incoming.empty() || s->stop) continue;
     if (!s->inflight.empty()) s->cv.wait_for(lk, std::chrono::microseconds(20));
     else s->cv.wait_for(lk, std::chrono::milliseconds(2));
@@ -455,7 +519,11 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
     for (int i = 0; i < kInflight; ++i) {
       if (s->staging[i]) (void)hipHostFree(s->staging[i]);
       if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+      if (s->ingested[i]) (void)hipEventDestroy(s->ingested[i]);
+      if (s->t_ingest[i]) (void)hipEventDestroy(s->t_ingest[i]);
+      if (s->t_decode[i]) (void)hipEventDestroy(s->t_decode[i]);
     }
+    if (s->ingest) (void)hipStreamDestroy(s->ingest);
     delete s->core;
     delete s;
     return status;
@@ -504,9 +572,19 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   for (int i = 0; i < kInflight; ++i) {
     e = hipHostMalloc(&s->staging[i], s->slot_bytes, hipHostMallocDefault);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostMalloc"));
-    e = hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming);
+    // timing events: the statistics report the device time of each iteration
+    e = hipEventCreate(&s->ev[i]);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
+    e = hipEventCreate(&s->ingested[i]);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
+    e = hipEventCreate(&s->t_ingest[i]);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
+    e = hipEventCreate(&s->t_decode[i]);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));
   }
+  // default priority, like every stream of the library
+  e = hipStreamCreateWithFlags(&s->ingest, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipStreamCreate"));
   try {
     vit::alloc_checkpoint();
     s->core = new vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames, cfg->max_items);
@@ -584,8 +662,15 @@ static int server_submit_impl(vit_server *s, const vit_request *reqs, int32_t co
     s->incoming.insert(s->incoming.end(), local.begin(), local.begin() + took);
     s->waiting += took;
     s->submitted += took;
-    for (int32_t i = 0; i < took; ++i)
+    for (int32_t i = 0; i < took; ++i) {
       if (s->first_arrival == 0 || local[i].arrival_ns < s->first_arrival) s->first_arrival = local[i].arrival_ns;
+      if (reqs[i].arrival_ns > 0) {  // a stated arrival time: how late it is handed over
+        const int64_t lag = now > reqs[i].arrival_ns ? now - reqs[i].arrival_ns : 0;
+        s->submit_lag += lag;
+        s->submit_lag_max = std::max(s->submit_lag_max, lag);
+        ++s->submit_lag_count;
+      }
+    }
   }
   if (took) s->cv.notify_one();
   if (accepted) *accepted = took;
@@ -666,6 +751,15 @@ static int server_stats_impl(vit_server *s, vit_serve_stats *st, int32_t reset) 
   st->peak_arena_bytes = s->peak_arena;
   st->first_arrival_ns = s->first_arrival;
   st->last_done_ns = s->last_done;
+  st->iter_ingest_ns = s->iter_ingest;
+  st->iter_decode_ns = s->iter_decode;
+  st->iter_max_ns = s->iter_max;
+  st->admit_wait_ns = s->admit_wait;
+  st->admit_wait_max_ns = s->admit_wait_max;
+  st->submit_lag_ns = s->submit_lag;
+  st->submit_lag_max_ns = s->submit_lag_max;
+  st->submit_lag_count = s->submit_lag_count;
+  st->engine_host_ns = s->engine_host;
   if (!s->lat.empty()) {
     vit::alloc_checkpoint();
     std::vector<int64_t> v(s->lat);
@@ -686,6 +780,10 @@ static int server_stats_impl(vit_server *s, vit_serve_stats *st, int32_t reset) 
     s->iterations = s->items_launched = 0;
     s->peak_arena = s->peak_frames = 0;
     s->first_arrival = s->last_done = 0;
+    s->iter_ingest = s->iter_decode = s->iter_max = 0;
+    s->admit_wait = s->admit_wait_max = 0;
+    s->submit_lag = s->submit_lag_max = s->submit_lag_count = 0;
+    s->engine_host = 0;
   }
   return VIT_OK;
 }
@@ -698,10 +796,16 @@ void vit_server_destroy(vit_server *s) {
   }
   s->cv.notify_all();
   if (s->engine.joinable()) s->engine.join();
+  // every iteration has retired, so its ingest (which its decode waited
+  // for) is complete too
   for (int i = 0; i < kInflight; ++i) {
     if (s->staging[i]) (void)hipHostFree(s->staging[i]);
     if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
+    if (s->ingested[i]) (void)hipEventDestroy(s->ingested[i]);
+    if (s->t_ingest[i]) (void)hipEventDestroy(s->t_ingest[i]);
+    if (s->t_decode[i]) (void)hipEventDestroy(s->t_decode[i]);
   }
+  if (s->ingest) (void)hipStreamDestroy(s->ingest);
   delete s->core;
   delete s;
 }

@@ -128,6 +128,7 @@ struct Iteration {
   std::vector<Copy> ingest, egress;
   std::vector<Frame> finishing;     // frames whose last block is in this iteration
   int64_t admitted = 0;
+  int64_t admit_wait_sum = 0, admit_wait_max = 0;  // admission time - arrival, ns, of its admitted frames
 };
 
 // A sink that collects the blocks into one vector, grouped by code (tests).
@@ -172,12 +173,15 @@ class Core {
   // Admit what fits, then schedule up to max_items blocks, handing each to
   // sink.put grouped by code after sink.begin(per-code counts, ncodes).
   // Returns false if there is nothing to launch (no blocks, no copies).
+  // now_ns: the admission time, for the admission waits of the admitted
+  // frames (0: not recorded).
   template <class Sink>
-  bool next_iteration(Iteration *it, Sink &sink) {
+  bool next_iteration(Iteration *it, Sink &sink, int64_t now_ns = 0) {
     it->ingest.clear();
     it->egress.clear();
     it->finishing.clear();
     it->admitted = 0;
+    it->admit_wait_sum = it->admit_wait_max = 0;
     while (!pending_.empty() && on_device_ < max_frames_) {
       Frame &f = pending_.front();
       int64_t id;
@@ -188,11 +192,14 @@ class Core {
       f.ring_id = id;
       f.next_cs = 0;
       it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
+      const int64_t w = (now_ns > 0 && now_ns > f.arrival_ns) ? now_ns - f.arrival_ns : 0;
       active_.push_back(f);
-      pending_.pop_front();
+      pending_.pop_front();  // (f refers to the popped frame from here on: not used again)
       ++on_device_;
       ++admitted_total_;
       ++it->admitted;
+      it->admit_wait_sum += w;
+      it->admit_wait_max = w > it->admit_wait_max ? w : it->admit_wait_max;
     }
     if (checkpoint) checkpoint();
     // Blocks per frame, in two passes over the active frames in admission
@@ -241,7 +248,9 @@ class Core {
     return it->nitems > 0 || !it->ingest.empty() || !it->egress.empty();
   }
 
-  bool next_iteration(Iteration *it, VectorSink &sink) { return next_iteration<VectorSink>(it, sink); }
+  bool next_iteration(Iteration *it, VectorSink &sink, int64_t now_ns = 0) {
+    return next_iteration<VectorSink>(it, sink, now_ns);
+  }
 
   // Drop every queued and admitted frame (after a device error), reporting
   // each to fn(frame, admitted); frames of launched iterations are not
