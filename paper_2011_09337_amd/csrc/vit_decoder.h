@@ -303,13 +303,18 @@ struct Decoder {
     // its decision XOR bit (pos mod P) of the slot index: following the
     // survivor then flips that bit of the traceback's slot index instead of
     // replacing it.
+    // Body offset pos = P*a + j sits at bit BODY-1-pos, so period a holds the
+    // slot's P bits reversed (bit P-1-j = slot bit j) at bit BODY-P-P*a: one
+    // reversed copy, repeated by a multiply (the copies do not overlap).
+    constexpr uint32_t kRep = [] {
+      uint32_t r = 0;
+      for (int a = 0; a < BODY / P; ++a) r |= 1u << (BODY - P - P * a);
+      return r;
+    }();
 #pragma unroll
     for (int reg = 0; reg < REGS; ++reg) {
-      const int st = ((reg << 6) | slot0) & (S - 1);
-      uint32_t m = 0;
-#pragma unroll
-      for (int pos = 0; pos < BODY; ++pos) m |= (uint32_t)((st >> (pos % P)) & 1) << (BODY - 1 - pos);
-      own_mask[reg] = m;
+      const uint32_t st = (uint32_t)(((reg << 6) | slot0) & (S - 1));
+      own_mask[reg] = (__builtin_bitreverse32(st) >> (32 - P)) * kRep;
     }
   }
 
@@ -921,12 +926,15 @@ template <int K, int BETA, bool STD, int IN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STD && K <= 7 ? 8 : 1, 8))) void vit_batch_kernel(BatchArgs a, int lds_words_per_wave) {
   using Dec = Decoder<K, BETA, STD, IN>;
   extern __shared__ uint32_t vit_lds[];
-  Dec D;
-  D.setup(a.gen);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
-  D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
   const int nitems = __builtin_amdgcn_readfirstlane(a.header[kMaxCodes + a.code_index]);
+  // waves without an item leave before any setup (fixed grids larger than
+  // the work list are cheap)
+  if ((int)blockIdx.x * wpb + wid >= nitems) return;
+  Dec D;
+  D.setup(a.gen);
+  D.lds = vit_lds + (size_t)wid * lds_words_per_wave;
   const WorkItem *items = a.items + a.header[2 * kMaxCodes + a.code_index];
   const int nwaves = (int)gridDim.x * wpb;
   for (int idx = (int)blockIdx.x * wpb + wid; idx < nitems; idx += nwaves) {

@@ -613,14 +613,16 @@ template <int K, int BETA, int IN>
 __global__ __launch_bounds__(256) void vit_batch16_kernel(BatchArgs a, int lds_words_per_wave) {
   using Dec = Decoder16<K, BETA, IN>;
   extern __shared__ uint32_t vit_lds16[];
-  Dec D;
-  D.setup(a.gen);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int wpb = (int)(blockDim.x >> 6);
-  D.lds = vit_lds16 + (size_t)wid * lds_words_per_wave;
   const int nitems = __builtin_amdgcn_readfirstlane(a.header[kMaxCodes + a.code_index]);
-  const WorkItem *items = a.items + a.header[2 * kMaxCodes + a.code_index];
   const int npairs = (nitems + 1) / 2;
+  // waves without a pair leave before any setup
+  if ((int)blockIdx.x * wpb + wid >= npairs) return;
+  Dec D;
+  D.setup(a.gen);
+  D.lds = vit_lds16 + (size_t)wid * lds_words_per_wave;
+  const WorkItem *items = a.items + a.header[2 * kMaxCodes + a.code_index];
   const int nwaves = (int)gridDim.x * wpb;
   for (int p = (int)blockIdx.x * wpb + wid; p < npairs; p += nwaves) {
     Blk16 bb[2];
