@@ -81,14 +81,15 @@ GEOMS = [
 SPLITS = [(1, 0, 0), (3, 2, 0), (8, 25, 1), (24, 7, 0), (31, 0, 1), (56, 45, 0), (40, 30, 1), (2000, 3, 0)]
 
 
+# every geometry with every split that leaves at most 64 subframes per block
+# (more are refused before any device work: test_too_many_subframes)
+SWEEP = [g + s for g in GEOMS for s in SPLITS if -(-(g[0] if g[1] == 0 else g[1]) // s[0]) <= 64]
+
+
 @pytest.mark.parametrize("name", list(CODES))
-@pytest.mark.parametrize("n,L,v,v1,terminated", GEOMS)
-@pytest.mark.parametrize("f0,w,rule", SPLITS)
+@pytest.mark.parametrize("n,L,v,v1,terminated,f0,w,rule", SWEEP)
 def test_geometry_sweep_awgn(dev, name, n, L, v, v1, terminated, f0, w, rule):
     k, gens = CODES[name]
-    Lb = n if L == 0 else L
-    if -(-Lb // f0) > 64:
-        pytest.skip("more than 64 subframes per block (refused; see test_too_many_subframes)")
     _, llr = _awgn(k, gens, n, 1.0, seed=n * 17 + L + v + 7 * f0 + w, terminated=terminated)
     _check(dev, k, gens, llr, n, L, v, f0, w, rule, seed=n + f0, v1=v1, terminated=terminated)
 
