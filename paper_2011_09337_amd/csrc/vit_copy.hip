@@ -1,7 +1,8 @@
-// vit_copy.hip -- gather/scatter of byte ranges listed in device memory, used
-// by the serving loop to move the LLRs of newly admitted frames from pinned
-// host memory into the device arena, and decoded bytes back, in one launch
-// per iteration however many frames it holds.
+// vit_copy.hip -- gather/scatter of byte ranges, used by the serving loop to
+// move its work list and the LLRs of newly admitted frames from pinned host
+// memory into the device, and decoded bytes back, in one launch per
+// iteration however many frames it holds.  The range list itself may sit in
+// device memory or in mapped pinned host memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -11,7 +12,8 @@ namespace vit {
 namespace {
 
 // One workgroup per range (grid-strided): 16-byte words when source,
-// destination and length allow, bytes otherwise.
+// destination and length allow, bytes otherwise.  Each thread has four words
+// in flight before it stores, since a read across PCIe takes microseconds.
 __global__ __launch_bounds__(256) void copy_list_kernel(const CopyRange *__restrict__ r, int32_t count) {
   for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
     const uint8_t *src = r[i].src;
@@ -20,9 +22,18 @@ __global__ __launch_bounds__(256) void copy_list_kernel(const CopyRange *__restr
     int64_t done = 0;
     if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
       const int64_t nw = bytes >> 4;
+      const int64_t bd = blockDim.x;
       const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
       uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-      for (int64_t j = threadIdx.x; j < nw; j += blockDim.x) d4[j] = s4[j];
+      int64_t j = threadIdx.x;
+      for (; j + 3 * bd < nw; j += 4 * bd) {
+        const uint4 a = s4[j], b = s4[j + bd], c = s4[j + 2 * bd], d = s4[j + 3 * bd];
+        d4[j] = a;
+        d4[j + bd] = b;
+        d4[j + 2 * bd] = c;
+        d4[j + 3 * bd] = d;
+      }
+      for (; j < nw; j += bd) d4[j] = s4[j];
       done = nw << 4;
     }
     for (int64_t j = done + threadIdx.x; j < bytes; j += blockDim.x) dst[j] = src[j];

@@ -55,10 +55,20 @@ int64_t mono_ns() {
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Per iteration slot: header | items | ingest ranges | egress ranges.
-size_t slot_bytes(int32_t max_frames, int32_t max_items) {
-  return round256(kHeaderBytes + (size_t)max_items * sizeof(vit::WorkItem) +
-                  2 * (size_t)max_frames * sizeof(vit::CopyRange));
+// The header and work items go up in pieces of this many bytes, one copy
+// range each, so that several workgroups of the copy kernel share them.
+constexpr size_t kItemChunk = 16384;
+
+// Device workspace per iteration slot: header | items.
+size_t slot_bytes(int32_t max_items) {
+  return round256(kHeaderBytes + (size_t)max_items * sizeof(vit::WorkItem));
+}
+size_t item_chunks(size_t bytes) { return (bytes + kItemChunk - 1) / kItemChunk; }
+// Pinned staging per slot: header | items | ranges for the header and items,
+// the ingest and the egress.  The copy kernels read the ranges in place.
+size_t staging_bytes(int32_t max_frames, int32_t max_items) {
+  const size_t items = slot_bytes(max_items);
+  return items + (item_chunks(items) + 2 * (size_t)max_frames) * sizeof(vit::CopyRange);
 }
 
 int check_config(const vit_server_config *cfg) {
@@ -118,6 +128,7 @@ struct vit_server {
   int64_t max_wait_ns = 0;  // queue timeout, 0 = none
 
   void *staging[kInflight] = {};
+  uint8_t *staging_dev[kInflight] = {};  // the same memory as the copy kernels address it
   hipEvent_t ev[kInflight] = {};         // the iteration is complete (decode and scatter)
   hipEvent_t ingested[kInflight] = {};   // its work list and LLRs are on the device
   hipEvent_t t_ingest[kInflight] = {};   // its ingest starts (timing)
@@ -194,25 +205,33 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     header[2 * kMaxCodes + c] = (int32_t)off;
     off += it.count[c];
   }
+  // ranges (in the staging, after the largest item list): the header and
+  // items in pieces, then the admitted frames' LLRs, then the egress
   const size_t items_end = kHeaderBytes + (size_t)it.nitems * sizeof(vit::WorkItem);
-  vit::CopyRange *cr = (vit::CopyRange *)(stg + items_end);
+  const size_t ranges_at = slot_bytes(s->max_items);
+  vit::CopyRange *cr = (vit::CopyRange *)(stg + ranges_at);
+  const size_t nchunk = item_chunks(items_end);
+  for (size_t i = 0; i < nchunk; ++i) {
+    const size_t at = i * kItemChunk;
+    cr[i] = {s->staging_dev[slot] + at, wsd + at, (int64_t)std::min(kItemChunk, items_end - at), 0};
+  }
+  vit::CopyRange *ir = cr + nchunk;
   for (size_t i = 0; i < it.ingest.size(); ++i)
-    cr[i] = {s->host_dev + it.ingest[i].src, s->arena + it.ingest[i].dst, it.ingest[i].bytes, 0};
-  vit::CopyRange *er = cr + it.ingest.size();
+    ir[i] = {s->host_dev + it.ingest[i].src, s->arena + it.ingest[i].dst, it.ingest[i].bytes, 0};
+  vit::CopyRange *er = ir + it.ingest.size();
   for (size_t i = 0; i < it.egress.size(); ++i)
     er[i] = {s->arena + it.egress[i].src, s->host_dev + it.egress[i].dst, it.egress[i].bytes, 0};
-  const size_t used = items_end + (it.ingest.size() + it.egress.size()) * sizeof(vit::CopyRange);
+  const vit::CopyRange *dcr = (const vit::CopyRange *)(s->staging_dev[slot] + ranges_at);
 
-  // ingest on the server's stream: it overlaps the decode of the iteration
-  // before (whose arena ranges and workspace slot it does not touch: slots
-  // are reused only after their iteration retired, and the ring allocator
-  // gives new frames free arena)
+  // ingest on the server's stream: one copy kernel gathers the work list and
+  // the new frames' LLRs from pinned host memory, reading its ranges there
+  // (no separate upload of the staging); it overlaps the decode of the
+  // iteration before, whose arena ranges and workspace slot it does not
+  // touch: slots are reused only after their iteration retired, and the
+  // ring allocator gives new frames free arena
   hipError_t e = hipEventRecord(s->t_ingest[slot], s->ingest);
   if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
-  e = hipMemcpyAsync(wsd, stg, used, hipMemcpyHostToDevice, s->ingest);
-  if (e != hipSuccess) return *msg = std::string("hipMemcpyAsync: ") + hipGetErrorString(e), VIT_EDEVICE;
-  const vit::CopyRange *dcr = (const vit::CopyRange *)(wsd + items_end);
-  e = vit::launch_copy_list(dcr, (int32_t)it.ingest.size(), s->ingest);
+  e = vit::launch_copy_list(dcr, (int32_t)(nchunk + it.ingest.size()), s->ingest);
   if (e != hipSuccess) return *msg = std::string("ingest: ") + hipGetErrorString(e), VIT_EDEVICE;
   e = hipEventRecord(s->ingested[slot], s->ingest);
   if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
@@ -236,7 +255,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
     if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
   }
-  e = vit::launch_copy_list(dcr + it.ingest.size(), (int32_t)it.egress.size(), s->stream);
+  e = vit::launch_copy_list(dcr + nchunk + it.ingest.size(), (int32_t)it.egress.size(), s->stream);
   if (e != hipSuccess) return *msg = std::string("egress: ") + hipGetErrorString(e), VIT_EDEVICE;
   e = hipEventRecord(s->ev[slot], s->stream);
   if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
@@ -373,10 +392,13 @@ void engine_loop(vit_server *s) {
     // next iteration instead of a small one of its own: every iteration
     // carries a fixed device cost (launches, the last blocks' tails), so
     // fewer, larger iterations carry more at high load, while at low load the
-    // ingests are short and the wait is too.
+    // ingests are short and the wait is too.  When the queue already holds
+    // more blocks than an iteration takes, waiting cannot make the next one
+    // larger: it is built at once, so that the host's work on it overlaps
+    // the ingest in flight.
     bool slot_free = (int)s->inflight.size() < kInflight;
     bool deferred = false;
-    if (slot_free && !s->inflight.empty() && s->core->has_work()) {
+    if (slot_free && !s->inflight.empty() && s->core->has_work() && s->core->pending_blocks() < s->max_items) {
       if (hipEventQuery(s->ingested[s->inflight.back()]) == hipErrorNotReady) {
         slot_free = false;
         deferred = true;
@@ -467,7 +489,7 @@ int vit_server_workspace_size(const vit_server_config *cfg, size_t *bytes) {
   int st = check_config(cfg);
   if (st) return st;
   if (!bytes) return api_fail(VIT_EINVAL, "bytes is NULL");
-  *bytes = kInflight * slot_bytes(cfg->max_frames, cfg->max_items);
+  *bytes = kInflight * slot_bytes(cfg->max_items);
   return VIT_OK;
 }
 
@@ -503,7 +525,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   if (!cfg->arena || !cfg->workspace || !cfg->host) return api_fail(VIT_EINVAL, "NULL arena, workspace or host region");
   if ((((uintptr_t)cfg->arena | (uintptr_t)cfg->workspace) & 255u) != 0)
     return api_fail(VIT_EINVAL, "arena and workspace must be 256-byte aligned");
-  const size_t need_ws = kInflight * slot_bytes(cfg->max_frames, cfg->max_items);
+  const size_t need_ws = kInflight * slot_bytes(cfg->max_items);
   if (cfg->workspace_bytes < need_ws)
     return api_fail(VIT_EINVAL, "workspace of %zu bytes, %zu needed", cfg->workspace_bytes, need_ws);
   if (cfg->arena_bytes < 256 || cfg->host_bytes < 1) return api_fail(VIT_EINVAL, "empty arena or host region");
@@ -542,7 +564,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   s->arena = (uint8_t *)cfg->arena;
   s->arena_bytes = cfg->arena_bytes;
   s->ws = (uint8_t *)cfg->workspace;
-  s->slot_bytes = slot_bytes(cfg->max_frames, cfg->max_items);
+  s->slot_bytes = slot_bytes(cfg->max_items);
   s->host = (uint8_t *)cfg->host;
   s->host_dev = (uint8_t *)hd;
   s->host_bytes = cfg->host_bytes;
@@ -570,8 +592,15 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
     shapes.push_back({codes[c].k, codes[c].beta, shape[c].L, v1, shape[c].v - v1});
   }
   for (int i = 0; i < kInflight; ++i) {
-    e = hipHostMalloc(&s->staging[i], s->slot_bytes, hipHostMallocDefault);
+    // coherent: the copy kernels read the ranges and items in place, and
+    // the host rewrites the slot every other iteration
+    e = hipHostMalloc(&s->staging[i], staging_bytes(cfg->max_frames, cfg->max_items),
+                      hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostMalloc"));
+    void *sd = nullptr;
+    e = hipHostGetDevicePointer(&sd, s->staging[i], 0);
+    if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipHostGetDevicePointer"));
+    s->staging_dev[i] = (uint8_t *)sd;
     // timing events: the statistics report the device time of each iteration
     e = hipEventCreate(&s->ev[i]);
     if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipEventCreate"));

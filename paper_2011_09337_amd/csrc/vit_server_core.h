@@ -156,8 +156,13 @@ class Core {
   int64_t arena_need(const Frame &f) const { return ring_.round(f.llr_bytes) + ring_.round((f.n + 7) / 8); }
   bool fits_ever(const Frame &f) const { return arena_need(f) <= ring_.capacity(); }
 
-  void submit(const Frame &f) { pending_.push_back(f); }
+  void submit(const Frame &f) {
+    pending_.push_back(f);
+    pending_blocks_ += blocks_of(f);
+  }
   size_t pending() const { return pending_.size(); }
+  // Blocks of the queued (not yet admitted) frames.
+  int64_t pending_blocks() const { return pending_blocks_; }
   size_t active() const { return active_.size(); }
   int64_t frames_on_device() const { return on_device_; }
   // Frames admitted since the core was made (monotonic): the engine derives
@@ -193,6 +198,7 @@ class Core {
       f.next_cs = 0;
       it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
       const int64_t w = (now_ns > 0 && now_ns > f.arrival_ns) ? now_ns - f.arrival_ns : 0;
+      pending_blocks_ -= blocks_of(f);
       active_.push_back(f);
       pending_.pop_front();  // (f refers to the popped frame from here on: not used again)
       ++on_device_;
@@ -259,6 +265,7 @@ class Core {
   void fail_all(Fn fn) {
     for (const Frame &f : pending_) fn(f, false);
     pending_.clear();
+    pending_blocks_ = 0;
     for (const Frame &f : active_) {
       fn(f, true);
       ring_.free(f.ring_id);
@@ -275,6 +282,7 @@ class Core {
     int64_t n = 0;
     while (!pending_.empty() && pending_.front().arrival_ns < cutoff_ns) {
       fn(pending_.front());
+      pending_blocks_ -= blocks_of(pending_.front());
       pending_.pop_front();
       ++n;
     }
@@ -290,6 +298,11 @@ class Core {
   }
 
  private:
+  int64_t blocks_of(const Frame &f) const {
+    const int64_t L = shapes_[f.code].L;
+    return (f.n + L - 1) / L;
+  }
+
   // Hand f's next `count` blocks (Sec. III geometry) to the sink.
   template <class Sink>
   void emit_blocks(Frame &f, int64_t count, Sink &sink) {
@@ -323,6 +336,7 @@ class Core {
   std::deque<Frame> active_;
   int64_t on_device_ = 0;
   int64_t admitted_total_ = 0;
+  int64_t pending_blocks_ = 0;
 };
 
 }  // namespace serve

@@ -103,6 +103,13 @@ int main(int argc, char **argv) {
 
   for (int64_t step = 0; finished < total; ++step) {
     CHECK(step < 10000000, "no progress");
+    if (step % 16 == 0) {  // the queue's block count: ceil(n / L) over the frames not yet admitted
+      int64_t want = 0;
+      for (const auto &kv : frames)
+        if (!kv.second.admitted) want += (kv.second.f.n + shapes[kv.second.f.code].L - 1) / shapes[kv.second.f.code].L;
+      CHECK(core.pending_blocks() == want, "pending blocks %lld, want %lld", (long long)core.pending_blocks(),
+            (long long)want);
+    }
     const int what = (int)(rng() % 4);
     if (what == 0 && submitted < total) {
       const int nsub = 1 + (int)(rng() % 8);
@@ -233,7 +240,8 @@ int main(int argc, char **argv) {
             (long long)core.frames_on_device(), on_device.size());
     }
   }
-  CHECK(!core.has_work() && inflight.empty() && core.arena_in_use() == 0, "work left at the end");
+  CHECK(!core.has_work() && inflight.empty() && core.arena_in_use() == 0 && core.pending_blocks() == 0,
+        "work left at the end");
 
   // queue timeouts: expire_queued drops expired frames from the front of the
   // queue only (an early arrival behind a live frame waits for its turn)
@@ -258,7 +266,8 @@ int main(int argc, char **argv) {
     auto note = [&](const Frame &f) { gone.push_back(f.tag); };
     CHECK(q.expire_queued(10, note) == 2 && gone.size() == 2 && gone[0] == 1000 && gone[1] == 1001,
           "expire at 10");
-    CHECK(q.pending() == 3, "pending after the first expiry");
+    const int64_t b16 = (16 + shapes[0].L - 1) / shapes[0].L;
+    CHECK(q.pending() == 3 && q.pending_blocks() == 3 * b16, "pending after the first expiry");
     CHECK(q.expire_queued(25, note) == 2 && gone[2] == 1002 && gone[3] == 1003, "expire at 25");
     CHECK(q.pending() == 1 && q.expire_queued(30, note) == 0, "arrival 30 is not before 30");
     Iteration it;
@@ -294,7 +303,8 @@ int main(int argc, char **argv) {
   int64_t dropped = 0;
   core.fail_all([&](const Frame &, bool) { ++dropped; });
   core.retire(it);
-  CHECK(!core.has_work() && core.frames_on_device() == 0 && core.arena_in_use() == 0, "fail_all left work");
+  CHECK(!core.has_work() && core.frames_on_device() == 0 && core.arena_in_use() == 0 && core.pending_blocks() == 0,
+        "fail_all left work");
   // an exception at the checkpoint after admission: the admitted frames stay
   // counted (admitted_total, frames_on_device) and fail_all reports each of
   // them once, as admitted, and each queued one once, as queued

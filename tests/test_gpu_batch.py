@@ -151,6 +151,43 @@ def test_graph_reuse_with_changing_frames(dev):
     b.close()
 
 
+def test_failed_rebuild_leaves_no_stale_shapes(dev):
+    # a good call builds the graph; a call whose second code cannot be planned
+    # (its blocks' survivors exceed the LDS) fails before any device work; the
+    # first call's shapes then decode a new frame list exactly: nothing of the
+    # failed call's launch planning stays in the plan
+    torch, vit = dev
+    rng = np.random.default_rng(31)
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    b = vit.Batch()
+    frames, llr, out_bytes, _ = make_batch(rng, 60, [0, 1, 2], 40, 3000)
+    t_llr = torch.from_numpy(llr).cuda()
+    out = torch.full((out_bytes,), 0xAB, dtype=torch.uint8, device="cuda")
+    print("[gpu] good call", flush=True)
+    b.decode(codes, frames, t_llr, out, tune=TUNE)
+    torch.cuda.synchronize()
+    check_frames(out.cpu().numpy(), frames, llr, TUNE)
+    bad = list(TUNE)
+    bad[1] = (60000, 35, -1, 1)
+    out.fill_(0xAB)
+    torch.cuda.synchronize()
+    print("[gpu] call failing on its second code", flush=True)
+    with pytest.raises(vit.VitError) as ei:
+        b.decode(codes, frames, t_llr, out, tune=bad)
+    assert ei.value.status == vit.VIT_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((out == 0xAB).all())
+    for trial in range(2):  # new frame lists: other item counts, so other grids
+        frames, llr, out_bytes, _ = make_batch(rng, 40 + 50 * trial, [0, 1, 2], 40, 3000)
+        t_llr = torch.from_numpy(llr).cuda()
+        out = torch.full((out_bytes,), 0xAB, dtype=torch.uint8, device="cuda")
+        print(f"[gpu] good call again ({len(frames)} frames)", flush=True)
+        b.decode(codes, frames, t_llr, out, tune=TUNE)
+        torch.cuda.synchronize()
+        check_frames(out.cpu().numpy(), frames, llr, TUNE)
+    b.close()
+
+
 def test_autotune_then_decode(dev):
     torch, vit = dev
     rng = np.random.default_rng(21)
