@@ -375,7 +375,9 @@ def bench_serving(vit, torch, args, tunes):
         srv.stats(reset=True)
         cap = None
         for rep in range(3):
-            nreq = P * (4 if rep == 0 else 16)  # a backlog long enough for the pipeline to fill
+            # a backlog long enough that filling and draining the pipeline
+            # (a few ms) is small beside the run (about 60 ms)
+            nreq = P * (4 if rep == 0 else 64)
             t0 = time.monotonic_ns()
             submit_all(requests(0, nreq))
             srv.drain(timeout_ms=120000)

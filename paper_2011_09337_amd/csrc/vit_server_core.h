@@ -107,7 +107,8 @@ struct Frame {
   int64_t arrival_ns;
   // set on admission
   int64_t arena_llr = -1, arena_out = -1, ring_id = 0;
-  int64_t next_cs = 0;  // first core bit not yet launched
+  int64_t next_cs = 0;      // first core bit not yet launched
+  int64_t blocks_left = 0;  // blocks not yet launched (set on submit)
 };
 
 struct Item {          // one block, in arena byte offsets
@@ -158,7 +159,10 @@ class Core {
 
   void submit(const Frame &f) {
     pending_.push_back(f);
-    pending_blocks_ += blocks_of(f);
+    Frame &q = pending_.back();
+    q.next_cs = 0;
+    q.blocks_left = blocks_of(f);
+    pending_blocks_ += q.blocks_left;
   }
   size_t pending() const { return pending_.size(); }
   // Blocks of the queued (not yet admitted) frames.
@@ -195,10 +199,9 @@ class Core {
       f.arena_llr = off;
       f.arena_out = off + ring_.round(f.llr_bytes);
       f.ring_id = id;
-      f.next_cs = 0;
       it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
       const int64_t w = (now_ns > 0 && now_ns > f.arrival_ns) ? now_ns - f.arrival_ns : 0;
-      pending_blocks_ -= blocks_of(f);
+      pending_blocks_ -= f.blocks_left;
       active_.push_back(f);
       pending_.pop_front();  // (f refers to the popped frame from here on: not used again)
       ++on_device_;
@@ -222,9 +225,7 @@ class Core {
     const int64_t share = na ? std::max<int64_t>(1, room / (int64_t)na) : 0;
     for (int pass = 0; pass < 2 && room > 0; ++pass) {
       for (size_t i = 0; i < na && room > 0; ++i) {
-        const Frame &f = active_[i];
-        const int64_t L = shapes_[f.code].L;
-        const int64_t left = (f.n - f.next_cs + L - 1) / L - take_[i];
+        const int64_t left = active_[i].blocks_left - take_[i];
         const int64_t t = std::min(left, pass == 0 ? std::min(share, room) : room);
         take_[i] += t;
         room -= t;
@@ -242,7 +243,7 @@ class Core {
     for (size_t i = 0; i < na; ++i) {
       Frame &f = active_[i];
       if (take_[i]) emit_blocks(f, take_[i], sink);
-      if (f.next_cs >= f.n) {
+      if (f.blocks_left == 0) {
         it->egress.push_back({f.arena_out, f.out_dst, (f.n + 7) / 8});
         it->finishing.push_back(f);
       } else {
@@ -282,7 +283,7 @@ class Core {
     int64_t n = 0;
     while (!pending_.empty() && pending_.front().arrival_ns < cutoff_ns) {
       fn(pending_.front());
-      pending_blocks_ -= blocks_of(pending_.front());
+      pending_blocks_ -= pending_.front().blocks_left;
       pending_.pop_front();
       ++n;
     }
@@ -325,6 +326,7 @@ class Core {
       sink.put(b);
       f.next_cs = ce;
     }
+    f.blocks_left -= count;
   }
 
   std::vector<CodeShape> shapes_;
@@ -333,7 +335,7 @@ class Core {
   Ring ring_;
   int max_frames_, max_items_;
   std::deque<Frame> pending_;
-  std::deque<Frame> active_;
+  std::vector<Frame> active_;  // admission order; compacted in place
   int64_t on_device_ = 0;
   int64_t admitted_total_ = 0;
   int64_t pending_blocks_ = 0;
