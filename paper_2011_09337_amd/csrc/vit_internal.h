@@ -116,8 +116,7 @@ struct CopyRange {
   int64_t bytes;
   int64_t pad;
 };
-// Copy `count` ranges listed in device or mapped pinned host memory
-// (vit_copy.hip).
+// Copy `count` ranges listed in device memory (vit_copy.hip).
 hipError_t launch_copy_list(const CopyRange *ranges, int32_t count, hipStream_t stream);
 
 // Launch the de-puncturer (vit_depuncture.hip): pattern bits mask[p*beta + b],
