@@ -329,11 +329,11 @@ int vit_plan_set_tune_tolerance(vit_plan *plan, double max_diff_fraction);
  * windows of Sec. III) taken from the admitted frames in arrival order.  A
  * long frame spreads over several iterations; frames that arrive while the
  * device is busy join the next one, and two iterations are in flight at
- * once.  Each iteration gathers its new frames' LLRs into the arena (on a
- * stream of the server's own, so that it overlaps the decode of the
- * iteration before), decodes its blocks with the persistent batch kernels
- * and scatters finished frames' decoded bytes back into the host region (on
- * the configured stream).  A frame's decoded bits are
+ * once.  Each iteration gathers its work list and its new frames' LLRs into
+ * the device (on a stream of the server's own, so that it overlaps the
+ * decode of the iteration before) and decodes its blocks with the batch
+ * kernels on the configured stream, which write the decoded bytes straight
+ * into the requests' places in the host region.  A frame's decoded bits are
  * identical to decoding it alone with vit_decode_ex and its code's
  * (L, v, v1); only the block is the unit of scheduling, and a block's path
  * metrics stay on chip.  Latency runs from the request's arrival time to the
@@ -349,7 +349,7 @@ typedef struct {
   int32_t max_wait_ms;       /* a request still queued (not admitted) this long after
                                 its arrival completes with VIT_ETIMEDOUT, undecoded;
                                 checked in queue order; 0 = no limit                 */
-  void *arena;               /* device, 256-aligned: admitted frames' LLRs + output  */
+  void *arena;               /* device, 256-aligned: admitted frames' LLRs           */
   size_t arena_bytes;        /* the memory budget that admission respects            */
   void *workspace;           /* device, 256-aligned, vit_server_workspace_size bytes */
   size_t workspace_bytes;
@@ -387,10 +387,10 @@ typedef struct {
   int64_t first_arrival_ns, last_done_ns;
   int64_t p50_ns, p99_ns, max_ns;   /* latency of completed frames */
   /* Where the time goes.  Device time per retired iteration, from events:
-   * its ingest (work-list copy and LLR gather on the server's stream) and its
-   * decode (batch kernels and scatter on the configured stream, from the
-   * moment that stream starts it); summed, and the longest iteration from
-   * ingest start to completion. */
+   * its ingest (work-list and LLR gather on the server's stream) and its
+   * decode (batch kernels on the configured stream, from the moment that
+   * stream starts it); summed, and the longest iteration from ingest start
+   * to completion. */
   int64_t iter_ingest_ns, iter_decode_ns, iter_max_ns;
   /* Admission wait (admission time - arrival), summed and largest. */
   int64_t admit_wait_ns, admit_wait_max_ns;

@@ -4,11 +4,11 @@
 // vit_server_submit.  An engine thread owned by the server runs iterations:
 // each admits queued frames while slots and device arena memory allow (the
 // scheduling lives in vit_server_core.h), then issues, on the server's own
-// ingest stream, one host-to-device copy of the iteration's work list and one
-// gather of the new frames' LLRs from the host region into the arena (over
-// PCIe), and on the caller's stream, after the ingest, one persistent batch
-// kernel per code over the iteration's blocks, one scatter of the finished
-// frames' decoded bytes into the host region, and an event.  Two iterations
+// ingest stream, one gather of the iteration's work list and of the new
+// frames' LLRs from the host region into the device (over PCIe), and on the
+// caller's stream, after the ingest, one batch kernel per code over the
+// iteration's blocks, which write the decoded bytes straight into the host
+// region, and an event.  Two iterations
 // are in flight at once, so requests that arrive while the device is busy
 // join the next iteration, and an iteration's ingest runs while the one
 // before it decodes.
@@ -64,11 +64,11 @@ size_t slot_bytes(int32_t max_items) {
   return round256(kHeaderBytes + (size_t)max_items * sizeof(vit::WorkItem));
 }
 size_t item_chunks(size_t bytes) { return (bytes + kItemChunk - 1) / kItemChunk; }
-// Pinned staging per slot: header | items | ranges for the header and items,
-// the ingest and the egress.  The copy kernels read the ranges in place.
+// Pinned staging per slot: header | items | ranges for the header and items
+// and for the ingest.  The copy kernel reads the ranges in place.
 size_t staging_bytes(int32_t max_frames, int32_t max_items) {
   const size_t items = slot_bytes(max_items);
-  return items + (item_chunks(items) + 2 * (size_t)max_frames) * sizeof(vit::CopyRange);
+  return items + (item_chunks(items) + (size_t)max_frames) * sizeof(vit::CopyRange);
 }
 
 int check_config(const vit_server_config *cfg) {
@@ -129,7 +129,7 @@ struct vit_server {
 
   void *staging[kInflight] = {};
   uint8_t *staging_dev[kInflight] = {};  // the same memory as the copy kernels address it
-  hipEvent_t ev[kInflight] = {};         // the iteration is complete (decode and scatter)
+  hipEvent_t ev[kInflight] = {};         // the iteration is complete (its decode has written every byte)
   hipEvent_t ingested[kInflight] = {};   // its work list and LLRs are on the device
   hipEvent_t t_ingest[kInflight] = {};   // its ingest starts (timing)
   hipEvent_t t_decode[kInflight] = {};   // its decode starts (timing)
@@ -206,7 +206,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     off += it.count[c];
   }
   // ranges (in the staging, after the largest item list): the header and
-  // items in pieces, then the admitted frames' LLRs, then the egress
+  // items in pieces, then the admitted frames' LLRs
   const size_t items_end = kHeaderBytes + (size_t)it.nitems * sizeof(vit::WorkItem);
   const size_t ranges_at = slot_bytes(s->max_items);
   vit::CopyRange *cr = (vit::CopyRange *)(stg + ranges_at);
@@ -218,9 +218,6 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
   vit::CopyRange *ir = cr + nchunk;
   for (size_t i = 0; i < it.ingest.size(); ++i)
     ir[i] = {s->host_dev + it.ingest[i].src, s->arena + it.ingest[i].dst, it.ingest[i].bytes, 0};
-  vit::CopyRange *er = ir + it.ingest.size();
-  for (size_t i = 0; i < it.egress.size(); ++i)
-    er[i] = {s->arena + it.egress[i].src, s->host_dev + it.egress[i].dst, it.egress[i].bytes, 0};
   const vit::CopyRange *dcr = (const vit::CopyRange *)(s->staging_dev[slot] + ranges_at);
 
   // ingest on the server's stream: one copy kernel gathers the work list and
@@ -243,7 +240,7 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     if (!it.count[c]) continue;
     vit::BatchArgs a;
     a.llr = s->arena;
-    a.out = s->arena;
+    a.out = s->host_dev;  // items carry each frame's output offset in the host region
     a.header = (int32_t *)wsd;
     a.items = (const vit::WorkItem *)(wsd + kHeaderBytes);
     a.code_index = c;
@@ -255,8 +252,6 @@ int launch_iteration(vit_server *s, const vit::serve::Iteration &it, int slot, s
     e = hipLaunchKernel(s->bl[c].fn, dim3(grid), dim3(s->bl[c].block), kargs, s->bl[c].lds, s->stream);
     if (e != hipSuccess) return *msg = std::string("decode launch: ") + hipGetErrorString(e), VIT_EDEVICE;
   }
-  e = vit::launch_copy_list(dcr + nchunk + it.ingest.size(), (int32_t)it.egress.size(), s->stream);
-  if (e != hipSuccess) return *msg = std::string("egress: ") + hipGetErrorString(e), VIT_EDEVICE;
   e = hipEventRecord(s->ev[slot], s->stream);
   if (e != hipSuccess) return *msg = std::string("hipEventRecord: ") + hipGetErrorString(e), VIT_EDEVICE;
   return VIT_OK;

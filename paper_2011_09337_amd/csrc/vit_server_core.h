@@ -3,8 +3,8 @@
 //
 // A request is one terminated or open frame.  The core keeps three sets:
 //   pending  -- submitted, waiting for a slot and arena memory (FIFO);
-//   active   -- admitted: its LLRs and decoded bytes have arena space on the
-//               device; some of its blocks are not yet launched;
+//   active   -- admitted: its LLRs have arena space on the device; some of
+//               its blocks are not yet launched;
 //   launched -- every block launched; finishes when its last iteration does.
 // An iteration admits what fits, then takes up to max_items blocks (the unit
 // of Sec. III: independent once the window's LLRs are present) from the
@@ -12,7 +12,8 @@
 // a long frame spreads over several iterations while new frames join the next
 // one and can finish first.  Decoding a block needs only
 // its LLR window, so between iterations a frame's device state is its arena
-// range (LLRs, decoded bytes); path metrics live on chip for one block.
+// range (its LLRs); path metrics live on chip for one block, and each block
+// writes its decoded bytes straight to the frame's place in the host region.
 #pragma once
 
 #include <stdint.h>
@@ -106,18 +107,18 @@ struct Frame {
   int64_t llr_bytes;
   int64_t arrival_ns;
   // set on admission
-  int64_t arena_llr = -1, arena_out = -1, ring_id = 0;
+  int64_t arena_llr = -1, ring_id = 0;
   int64_t next_cs = 0;      // first core bit not yet launched
   int64_t blocks_left = 0;  // blocks not yet launched (set on submit)
 };
 
-struct Item {          // one block, in arena byte offsets
+struct Item {          // one block: LLRs at an arena offset, output at a host-region offset
   int code;
   int64_t llr_off, out_off;
   int32_t s, e, cs, ce, flags, cost;
 };
 
-struct Copy {          // a byte range to move (ingest: host -> arena; egress: arena -> host)
+struct Copy {          // a byte range to move (ingest: host -> arena)
   int64_t src, dst, bytes;
 };
 
@@ -126,7 +127,7 @@ constexpr int kMaxShapes = 8;
 struct Iteration {
   int64_t count[kMaxShapes] = {0};  // blocks per code, handed to the sink grouped by code
   int64_t nitems = 0;
-  std::vector<Copy> ingest, egress;
+  std::vector<Copy> ingest;
   std::vector<Frame> finishing;     // frames whose last block is in this iteration
   int64_t admitted = 0;
   int64_t admit_wait_sum = 0, admit_wait_max = 0;  // admission time - arrival, ns, of its admitted frames
@@ -153,8 +154,8 @@ class Core {
       : shapes_(std::move(shapes)), elem_(elem_bytes), ring_(arena_bytes), max_frames_(max_frames),
         max_items_(max_items) {}
 
-  // Arena bytes a frame needs (LLRs and decoded bytes, each 256-aligned).
-  int64_t arena_need(const Frame &f) const { return ring_.round(f.llr_bytes) + ring_.round((f.n + 7) / 8); }
+  // Arena bytes a frame needs (its LLRs, 256-aligned).
+  int64_t arena_need(const Frame &f) const { return ring_.round(f.llr_bytes); }
   bool fits_ever(const Frame &f) const { return arena_need(f) <= ring_.capacity(); }
 
   void submit(const Frame &f) {
@@ -187,7 +188,6 @@ class Core {
   template <class Sink>
   bool next_iteration(Iteration *it, Sink &sink, int64_t now_ns = 0) {
     it->ingest.clear();
-    it->egress.clear();
     it->finishing.clear();
     it->admitted = 0;
     it->admit_wait_sum = it->admit_wait_max = 0;
@@ -197,7 +197,6 @@ class Core {
       const int64_t off = ring_.alloc(arena_need(f), &id);
       if (off < 0) break;
       f.arena_llr = off;
-      f.arena_out = off + ring_.round(f.llr_bytes);
       f.ring_id = id;
       it->ingest.push_back({f.llr_src, f.arena_llr, f.llr_bytes});
       const int64_t w = (now_ns > 0 && now_ns > f.arrival_ns) ? now_ns - f.arrival_ns : 0;
@@ -219,7 +218,6 @@ class Core {
     take_.assign(na, 0);
     // room for every frame to finish, so that the compaction below cannot
     // throw half-way
-    it->egress.reserve(na);
     it->finishing.reserve(na);
     int64_t room = max_items_;
     const int64_t share = na ? std::max<int64_t>(1, room / (int64_t)na) : 0;
@@ -244,7 +242,6 @@ class Core {
       Frame &f = active_[i];
       if (take_[i]) emit_blocks(f, take_[i], sink);
       if (f.blocks_left == 0) {
-        it->egress.push_back({f.arena_out, f.out_dst, (f.n + 7) / 8});
         it->finishing.push_back(f);
       } else {
         if (keep != i) active_[keep] = f;
@@ -252,7 +249,7 @@ class Core {
       }
     }
     active_.resize(keep);
-    return it->nitems > 0 || !it->ingest.empty() || !it->egress.empty();
+    return it->nitems > 0 || !it->ingest.empty();
   }
 
   bool next_iteration(Iteration *it, VectorSink &sink, int64_t now_ns = 0) {
@@ -311,7 +308,7 @@ class Core {
     Item b;
     b.code = f.code;
     b.llr_off = f.arena_llr;
-    b.out_off = f.arena_out;
+    b.out_off = f.out_dst;
     for (int64_t taken = 0; taken < count; ++taken) {
       const int64_t cs = f.next_cs;
       const int64_t ce = std::min(cs + sh.L, f.n);

@@ -3,7 +3,8 @@
 // moments.  Every invariant the HIP engine relies on is asserted here:
 // block geometry per frame (blocked decoding with overlap), each core bit
 // launched exactly once and in order, ingest no later than a frame's first
-// block, egress in the iteration of its last block, arena ranges of frames on
+// block, completion in the iteration of its last block, items writing to the
+// frame's own output place, arena ranges of frames on
 // the device pairwise disjoint and inside the arena, slot and item limits,
 // FIFO admission, a block for every waiting frame when the iteration has room
 // for one each, and eventual completion.
@@ -135,7 +136,7 @@ int main(int argc, char **argv) {
       Iteration it;
       VectorSink sink;
       if (!core.next_iteration(&it, sink)) {
-        CHECK(sink.items.empty() && it.ingest.empty() && it.egress.empty(), "empty iteration with work");
+        CHECK(sink.items.empty() && it.ingest.empty(), "empty iteration with work");
         continue;
       }
       const std::vector<Item> &items = sink.items;
@@ -154,7 +155,7 @@ int main(int argc, char **argv) {
         CHECK(c.src == t.f.llr_src && c.bytes == t.f.llr_bytes, "ingest of frame %llu not in FIFO order",
               (unsigned long long)tag);
         CHECK(c.dst % 256 == 0 && c.dst >= 0, "ingest destination misaligned");
-        const int64_t end = c.dst + ((c.bytes + 255) / 256) * 256 + (((t.f.n + 7) / 8 + 255) / 256) * 256;
+        const int64_t end = c.dst + ((c.bytes + 255) / 256) * 256;
         CHECK(end <= arena, "frame arena range beyond the arena");
         for (const auto &kv : on_device)
           CHECK(end <= kv.second.first || kv.second.second <= c.dst, "arena ranges of frames %llu and %llu overlap",
@@ -164,7 +165,6 @@ int main(int argc, char **argv) {
         t.admitted = true;
         t.admit_order = admitted_so_far++;
         t.f.arena_llr = c.dst;
-        t.f.arena_out = c.dst + ((c.bytes + 255) / 256) * 256;
       }
       CHECK((int64_t)on_device.size() <= max_frames, "%zu frames on device > %d", on_device.size(), max_frames);
       // items: geometry, order, grouping
@@ -178,7 +178,7 @@ int main(int argc, char **argv) {
         }
         CHECK(by_arena.count(b.llr_off), "item of a frame not on the device");
         Truth &t = frames[by_arena[b.llr_off]];
-        CHECK(t.ingested && b.code == t.f.code && b.out_off == t.f.arena_out, "item addresses");
+        CHECK(t.ingested && b.code == t.f.code && b.out_off == t.f.out_dst, "item addresses");
       }
       // per frame, blocks in order (items are sorted, so collect first)
       std::map<uint64_t, std::vector<Item>> per;
@@ -208,15 +208,14 @@ int main(int argc, char **argv) {
           t.next_cs = ce;
         }
       }
-      // egress: exactly the frames whose last block is in this iteration
+      // finishing: exactly the frames whose last block is in this iteration
       std::set<uint64_t> fin;
       for (const Frame &f : it.finishing) fin.insert(f.tag);
-      CHECK(fin.size() == it.egress.size(), "egress count");
+      CHECK(fin.size() == it.finishing.size(), "a frame finishing twice in one iteration");
       for (size_t i = 0; i < it.finishing.size(); ++i) {
         Truth &t = frames[it.finishing[i].tag];
         CHECK(t.next_cs == t.f.n, "frame %llu finishing with bits left", (unsigned long long)t.f.tag);
-        CHECK(it.egress[i].src == t.f.arena_out && it.egress[i].dst == t.f.out_dst &&
-              it.egress[i].bytes == (t.f.n + 7) / 8, "egress range");
+        CHECK(per.count(t.f.tag), "frame %llu finishing without a block in the iteration", (unsigned long long)t.f.tag);
       }
       for (auto &kv : frames)
         if (kv.second.admitted && !kv.second.finished && kv.second.next_cs == kv.second.f.n)
