@@ -99,6 +99,7 @@ def test_mix_equals_alone_and_oracle(dev, int8, metric_bits):
     # memory and long frames span several iterations
     srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8 if int8 else vit.VIT_LLR_F32,
                      arena_bytes=96 << 10, max_frames=10, max_items=48, metric_bits=metric_bits)
+    before = host.numpy().copy()
     try:
         order = rng.permutation(len(frames))
         for wave in np.array_split(order, 8):
@@ -120,6 +121,11 @@ def test_mix_equals_alone_and_oracle(dev, int8, metric_bits):
     assert stats["peak_arena_bytes"] <= 96 << 10
     assert 0 < stats["p50_ns"] <= stats["p99_ns"] <= stats["max_ns"]
     h = host.numpy()
+    # the decode writes into the host region only the requests' output bytes
+    outside = np.ones(h.size, dtype=bool)
+    for t, fr in enumerate(frames):
+        outside[offs[t][1]:offs[t][1] + (fr[2] + 7) // 8] = False
+    np.testing.assert_array_equal(h[outside], before[outside], err_msg="bytes outside the outputs changed")
     for t, fr in enumerate(frames):
         lo, oo = offs[t]
         got = h[oo:oo + (fr[2] + 7) // 8]
