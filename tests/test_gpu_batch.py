@@ -69,7 +69,13 @@ def run_batch(dev, batch, frames, llr, out_bytes, code_ids, tune):
     print(f"[gpu] batch of {len(frames)} frames, tune={tune}", flush=True)
     batch.decode(codes, frames, t_llr, out, tune=tune)
     torch.cuda.synchronize()
-    return out.cpu().numpy()
+    got = out.cpu().numpy()
+    # bytes between the frames' outputs keep the fill
+    outside = np.ones(out_bytes, dtype=bool)
+    for fr in frames:
+        outside[fr[4]:fr[4] + (fr[2] + 7) // 8] = False
+    assert (got[outside] == 0xAB).all(), "a byte outside the frames' outputs was written"
+    return got
 
 
 def check_frames(got, frames, llr, tunes):
