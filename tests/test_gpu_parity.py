@@ -44,9 +44,14 @@ def _gpu(dev, k, gens, llr, n, L, v, v1=None, terminated=True, stream=None):
     t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
     print(f"[gpu] k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} term={terminated} "
           f"dtype={llr.dtype}", flush=True)
-    out = vit.decode(code, t, n, L, v, v1=v1, terminated=terminated, stream=stream)
+    nb = (n + 7) // 8
+    buf = torch.full((nb + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()  # the fill is on torch's stream, the decode may be on another
+    vit.decode(code, t, n, L, v, v1=v1, terminated=terminated, stream=stream, out=buf)
     torch.cuda.synchronize()
-    return out.cpu().numpy()
+    got = buf.cpu().numpy()
+    assert (got[nb:] == 0xAB).all(), "the decode wrote past ceil(n/8) bytes"
+    return got[:nb]
 
 
 def _oracle(k, gens, llr, n, L, v, v1=None, terminated=True):
