@@ -41,10 +41,14 @@ def _check(dev, k, gens, llr, n, L, v, f0, w, rule=0, seed=0, v1=None, terminate
     print(f"[gpu] k={k} gens={[oct(g) for g in gens]} n={n} L={L} v={v} v1={v1} f0={f0} w={w} rule={rule} "
           f"seed={seed} term={terminated} dtype={llr.dtype}", flush=True)
     t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
-    got = vit.decode(vit.make_code(k, gens), t, n, L, v, v1=v1, terminated=terminated, subframe_bits=f0,
-                     subframe_overlap=w, subframe_start=rule, subframe_seed=seed)
+    nb = (n + 7) // 8
+    buf = torch.full((nb + 64,), 0xAB, dtype=torch.uint8, device="cuda")
+    vit.decode(vit.make_code(k, gens), t, n, L, v, v1=v1, terminated=terminated, subframe_bits=f0,
+               subframe_overlap=w, subframe_start=rule, subframe_seed=seed, out=buf)
     torch.cuda.synchronize()
-    got = got.cpu().numpy()
+    got = buf.cpu().numpy()
+    assert (got[nb:] == 0xAB).all(), "the decode wrote past ceil(n/8) bytes"
+    got = got[:nb]
     e1 = v // 2 if v1 is None else v1
     code = vref.make_code(k, list(gens))
     ol = llr
