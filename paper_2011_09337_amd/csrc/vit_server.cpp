@@ -611,7 +611,7 @@ static int server_create_impl(const vit_code *codes, int32_t ncodes, const vit_t
   if (e != hipSuccess) return bail(vit::api_fail_hip(e, "hipStreamCreate"));
   try {
     vit::alloc_checkpoint();
-    s->core = new vit::serve::Core(shapes, s->elem, (int64_t)cfg->arena_bytes, cfg->max_frames, cfg->max_items);
+    s->core = new vit::serve::Core(shapes, (int64_t)cfg->arena_bytes, cfg->max_frames, cfg->max_items);
     s->core->checkpoint = &vit::alloc_checkpoint;
   } catch (const std::bad_alloc &) {
     return bail(api_fail(VIT_ENOMEM, "core allocation failed"));

@@ -150,8 +150,8 @@ struct VectorSink {
 
 class Core {
  public:
-  Core(std::vector<CodeShape> shapes, int elem_bytes, int64_t arena_bytes, int max_frames, int max_items)
-      : shapes_(std::move(shapes)), elem_(elem_bytes), ring_(arena_bytes), max_frames_(max_frames),
+  Core(std::vector<CodeShape> shapes, int64_t arena_bytes, int max_frames, int max_items)
+      : shapes_(std::move(shapes)), ring_(arena_bytes), max_frames_(max_frames),
         max_items_(max_items) {}
 
   // Arena bytes a frame needs (its LLRs, 256-aligned).
@@ -328,7 +328,6 @@ class Core {
 
   std::vector<CodeShape> shapes_;
   std::vector<int64_t> take_;
-  int elem_;
   Ring ring_;
   int max_frames_, max_items_;
   std::deque<Frame> pending_;

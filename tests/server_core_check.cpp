@@ -84,7 +84,7 @@ int main(int argc, char **argv) {
   const int64_t arena = 256 * (64 + (int64_t)(rng() % 4096));
   const int max_frames = 1 + (int)(rng() % 64);
   const int max_items = 1 + (int)(rng() % 300);
-  Core core(shapes, elem, arena, max_frames, max_items);
+  Core core(shapes, arena, max_frames, max_items);
 
   struct Truth {
     Frame f;
@@ -245,7 +245,7 @@ int main(int argc, char **argv) {
   // queue timeouts: expire_queued drops expired frames from the front of the
   // queue only (an early arrival behind a live frame waits for its turn)
   {
-    Core q(shapes, elem, arena, max_frames, max_items);
+    Core q(shapes, arena, max_frames, max_items);
     const int64_t arrivals[5] = {5, 7, 20, 3, 30};
     for (int j = 0; j < 5; ++j) {
       Frame f;
@@ -308,7 +308,7 @@ int main(int argc, char **argv) {
   // counted (admitted_total, frames_on_device) and fail_all reports each of
   // them once, as admitted, and each queued one once, as queued
   {
-    Core x(shapes, elem, arena, max_frames, max_items);
+    Core x(shapes, arena, max_frames, max_items);
     struct Boom {};
     static bool armed;
     armed = true;
