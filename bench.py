@@ -74,6 +74,8 @@ def parse():
                     help="seconds per serving load point (the serving configuration runs 60 s)")
     ap.add_argument("--serve-pool", type=int, default=4096)
     ap.add_argument("--serve-arena-mb", type=int, default=256)
+    ap.add_argument("--serve-max-items", type=int, default=1 << 16,
+                    help="blocks per serving iteration at most")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -342,7 +344,7 @@ def bench_serving(vit, torch, args, tunes):
     frames, host = serving_pool(vit, torch, args.serve_pool)
     codes = [vit.make_code(*synth.CODES[c]) for c in BATCH_CODES]
     srv = vit.Server(codes, host, tune=tunes, llr_type=vit.VIT_LLR_I8, arena_bytes=args.serve_arena_mb << 20,
-                     max_frames=1 << 16, max_items=1 << 16, max_pending=1 << 24)
+                     max_frames=1 << 16, max_items=args.serve_max_items, max_pending=1 << 24)
     base = host.data_ptr()
     P = len(frames)
     pool = np.zeros(P, dtype=vit.REQUEST_DTYPE)
@@ -473,6 +475,7 @@ def bench_serving(vit, torch, args, tunes):
         "capacity_mbps": round(cap * mean_bits / 1e6, 2),
         "capacity_alu_frac": round(cap * mean_work / 1e12 / ALU_PEAK_TOPS, 4),
         "arena_MiB": args.serve_arena_mb,
+        "max_items": args.serve_max_items,
         "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
         "points": points,
     }
