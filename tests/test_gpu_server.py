@@ -135,6 +135,35 @@ def test_mix_equals_alone_and_oracle(dev, int8, metric_bits):
             np.testing.assert_array_equal(got, expected_oracle(fr, TUNE), err_msg=f"frame {t} vs oracle")
 
 
+def test_mix_hard_decisions(dev):
+    # hard-decision requests (one byte per coded bit) through the serving loop:
+    # each frame equals its decode alone and the oracle's on +1 / -1 LLRs
+    torch, vit = dev
+    rng = np.random.default_rng(13)
+    soft = make_frames(rng, 60, 20, 2000, False)
+    frames = [(cid, term, n, synth.hard_bits(llr)) for cid, term, n, llr in soft]
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_HARD, arena_bytes=96 << 10, max_frames=10,
+                     max_items=48)
+    try:
+        st, acc = srv.submit(requests(vit, host, frames, offs, list(range(len(frames)))))
+        assert st == vit.VIT_OK and acc == len(frames)
+        srv.drain(timeout_ms=60000)
+        comps = srv.poll()
+    finally:
+        srv.close()
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames)))
+    assert (comps["status"] == 0).all()
+    h = host.numpy()
+    for t, (cid, term, n, hard) in enumerate(frames):
+        oo = offs[t][1]
+        got = h[oo:oo + (n + 7) // 8]
+        np.testing.assert_array_equal(got, expected_alone(torch, vit, frames[t], TUNE), err_msg=f"frame {t} alone")
+        pm1 = np.where(hard != 0, -1, 1).astype(np.int8)
+        np.testing.assert_array_equal(got, expected_oracle((cid, term, n, pm1), TUNE), err_msg=f"frame {t} oracle")
+
+
 def test_late_short_frames_overtake_a_long_one(dev):
     torch, vit = dev
     rng = np.random.default_rng(5)
