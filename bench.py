@@ -239,14 +239,15 @@ def bench_batched(vit, torch, args):
     stream = torch.cuda.current_stream()
     steps = max(3, args.steps // 2)
 
-    def time_batch(plan, fr):
+    def time_batch(plan, fr, tu=None):
+        tu = tunes if tu is None else tu
         for _ in range(2):
-            plan.decode(codes, fr, q_d, out, tune=tunes, stream=stream)
+            plan.decode(codes, fr, q_d, out, tune=tu, stream=stream)
         torch.cuda.synchronize()
         s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s0.record(stream)
         for _ in range(steps):
-            plan.decode(codes, fr, q_d, out, tune=tunes, stream=stream)
+            plan.decode(codes, fr, q_d, out, tune=tu, stream=stream)
         s1.record(stream)
         torch.cuda.synchronize()
         return s0.elapsed_time(s1) / steps
@@ -263,10 +264,22 @@ def bench_batched(vit, torch, args):
         work_c = 4.0 * batch_stages(fl, tunes)
         per_code[name] = {"frames": len(fl), "mbps": round(bits_c / (ms_c * 1e-3) / 1e6, 1),
                           "ms": round(ms_c, 4), "alu_frac": round(work_c / (ms_c * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4)}
-    # the same batch and shapes with 16-bit modulo path metrics
+    # the same batch and shapes with 16-bit modulo path metrics, then with
+    # shapes autotuned for them (a 16-bit wave holds two blocks, so its best
+    # shapes differ)
     b16 = vit.Batch(metric_bits=16)
     ms16 = time_batch(b16, frames_np)
     out16 = out.cpu().numpy()
+    int16_tuned = None
+    if not args.batched_tune:
+        tunes16 = b16.autotune(codes, frames_np, q_d, out)
+        ms16t = time_batch(b16, frames_np, tunes16)
+        int16_tuned = {"mbps": round(sum(f[2] for f in frames) / (ms16t * 1e-3) / 1e6, 2),
+                       "ms_per_step": round(ms16t, 4),
+                       "alu_frac": round(4.0 * batch_stages(frames, tunes16) / (ms16t * 1e-3) / 1e12 / ALU_PEAK_TOPS,
+                                         4),
+                       "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]}
+                                  for i, t in enumerate(tunes16)}}
     b16.close()
     ms = time_batch(b, frames_np)
     got = out.cpu().numpy()
@@ -294,7 +307,7 @@ def bench_batched(vit, torch, args):
         "per_code": per_code,
         "int16": {"mbps": round(nbits / (ms16 * 1e-3) / 1e6, 2), "ms_per_step": round(ms16, 4),
                   "alu_frac": round(work / (ms16 * 1e-3) / 1e12 / ALU_PEAK_TOPS, 4),
-                  "bits_equal_to_32": bool(np.array_equal(out16, got))},
+                  "bits_equal_to_32": bool(np.array_equal(out16, got)), "own_tuning": int16_tuned},
         "tuning": {BATCH_CODES[i]: {"L": t[0], "v": t[1], "waves_per_block": t[3]} for i, t in enumerate(tunes)},
         "ber_int8": err8 / nbits,
         "ber_fp32_same_shapes": err32 / nbits,
