@@ -241,6 +241,49 @@ def test_full_size_stream_k7(dev, L):
     _check(dev, k, gens, llr, n, L, 35)
 
 
+# ----------------------------------------------------------------------------- maximum size
+
+@pytest.mark.parametrize("kind", ["i8", "f32"])
+def test_maximum_stream_size_sampled(dev, kind):
+    # a K=7 r1/2 stream just under the library's limits (2^32 LLR bytes and
+    # 2^31 stages), where the kernels' 32-bit byte offsets are at their
+    # largest: integer-valued LLRs drawn on the device (so that the oracle's
+    # window decoder in float64 is exact), sampled blocks, the last ones
+    # included, against the oracle's decode of each block's window
+    torch, vit = dev
+    k, gens = CODES["k7r12"]
+    code = vit.make_code(k, gens)
+    ocode = vref.make_code(k, list(gens))
+    L, v = 512, 35
+    v1, v2 = v // 2, v - v // 2
+    elem = 1 if kind == "i8" else 4
+    N = ((1 << 32) - 64) // (2 * elem)
+    N = min(N, (1 << 31) - 64)
+    n = N - (k - 1)
+    print(f"[gpu] maximum size {kind}: n={n} N={N} LLR bytes={2 * N * elem}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2024)
+    if kind == "i8":
+        llr = torch.randint(-127, 128, (2 * N,), dtype=torch.int8, device="cuda", generator=g)
+    else:
+        llr = torch.randint(-40, 41, (2 * N,), dtype=torch.int32, device="cuda", generator=g).to(torch.float32)
+    out = vit.decode(code, llr, n, L, v)
+    torch.cuda.synchronize()
+    nblocks = -(-n // L)
+    rng = np.random.default_rng(5)
+    picks = sorted(set([0, 1, nblocks // 2] + rng.integers(2, nblocks - 3, size=8).tolist()
+                       + [nblocks - 3, nblocks - 2, nblocks - 1]))
+    for b in picks:
+        cs, ce = b * L, min(b * L + L, n)
+        s, e = max(0, cs - v1), min(N, ce + v2)
+        w = llr[2 * s:2 * e].cpu().numpy().astype(np.float64)
+        want, _ = vref.window_f64(ocode, w, 0, e - s, s == 0, e == N, cs - s, ce - s)
+        got = synth.unpack_bits(out[cs // 8:(ce + 7) // 8].cpu().numpy(), ce - cs)
+        np.testing.assert_array_equal(got, want, err_msg=f"block {b} of {nblocks} ({kind})")
+    del llr, out
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------------------- BER-gap reference
 
 @pytest.mark.parametrize("ebn0", [2.5, 3.5, 4.5])
