@@ -194,6 +194,61 @@ def test_failed_rebuild_leaves_no_stale_shapes(dev):
     b.close()
 
 
+def test_frames_beyond_4gib_offsets(dev):
+    # frames whose LLRs sit beyond 2^31 and 2^32 bytes into the batch's LLR
+    # buffer and whose outputs sit beyond 2^31 bytes into the output buffer:
+    # the work items' 64-bit offsets; every frame equals the oracle's decode
+    # of that frame alone, through the plan and through the allocation-free
+    # entry point
+    torch, vit = dev
+    rng = np.random.default_rng(41)
+    # LLR ranges (at most 18 KB each) straddling 2^31 and 2^32, outputs (at
+    # most 750 bytes each) straddling 2^31; no two ranges overlap
+    offsets = [0, (1 << 31) - 5001, (1 << 31) + 40013, (1 << 32) - 7001, (1 << 32) + (1 << 29) + 1]
+    outs = [0, 1000, (1 << 31) - 300, (1 << 31) + 1000, (1 << 31) + 5000]
+    llr_bytes = offsets[-1] + 40000
+    out_bytes = outs[-1] + 10000
+    print(f"[gpu] batch beyond 4 GiB: LLR buffer {llr_bytes} B, output buffer {out_bytes} B", flush=True)
+    t_llr = torch.zeros(llr_bytes, dtype=torch.int8, device="cuda")
+    frames, olls = [], []
+    for i, (lo, oo) in enumerate(zip(offsets, outs)):
+        cid = i % 3
+        k, gens = CODES[cid]
+        n = int(rng.integers(500, 6000))
+        e = float(rng.uniform(1.0, 4.0))
+        llr = vref.quantize_i8(synth.awgn_llr(synth.encode(k, gens, synth.info_bits(n, rng), True), e, len(gens),
+                                              rng), 4.0)
+        t_llr[lo:lo + llr.size] = torch.from_numpy(llr).cuda()
+        frames.append((cid, 1, n, lo, oo))
+        olls.append(llr)
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    for path in ("plan", "static"):
+        out = torch.full((out_bytes,), 0xAB, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        print(f"[gpu] batch beyond 4 GiB via {path}", flush=True)
+        if path == "plan":
+            b = vit.Batch()
+            b.decode(codes, frames, t_llr, out, tune=TUNE)
+            torch.cuda.synchronize()
+            b.close()
+        else:
+            vit.vit_decode_batch_static(vit.codes_array(codes), vit.frames_array(frames), t_llr.data_ptr(),
+                                        t_llr.numel(), vit.VIT_LLR_I8, out.data_ptr(), out.numel(),
+                                        vit.tunings_array(TUNE), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+        for (cid, term, n, lo, oo), llr in zip(frames, olls):
+            k, gens = CODES[cid]
+            L, v, v1, _ = TUNE[cid]
+            v1 = v // 2 if v1 < 0 else v1
+            want = synth.pack_bits(vref.decode_blocked(vref.make_code(k, list(gens)), llr, n, L, v1, v - v1, True,
+                                                       nthreads=NCPU))
+            got = out[oo:oo + want.size].cpu().numpy()
+            np.testing.assert_array_equal(got, want, err_msg=f"{path}: frame at LLR offset {lo}")
+        del out
+    del t_llr
+    torch.cuda.empty_cache()
+
+
 def test_autotune_then_decode(dev):
     torch, vit = dev
     rng = np.random.default_rng(21)
