@@ -164,6 +164,42 @@ def test_mix_hard_decisions(dev):
         np.testing.assert_array_equal(got, expected_oracle((cid, term, n, pm1), TUNE), err_msg=f"frame {t} oracle")
 
 
+def test_requests_beyond_4gib_in_the_host_region(dev):
+    # requests whose LLRs and outputs sit beyond 2^31 and 2^32 bytes into a
+    # 4.3 GB pinned host region (ranges straddling both): the ingest copies'
+    # and the direct output writes' 64-bit addresses
+    torch, vit = dev
+    rng = np.random.default_rng(17)
+    frames = make_frames(rng, 5, 500, 4000, True)
+    offs_llr = [0, (1 << 31) - 5001, (1 << 31) + 40013, (1 << 32) - 7001, (1 << 32) + 20011]
+    offs = []
+    for (_, _, n, llr), lo in zip(frames, offs_llr):
+        offs.append((lo, lo + llr.nbytes + 3))  # the output right after the LLRs
+    size = max(oo + (f[2] + 7) // 8 for f, (_, oo) in zip(frames, offs)) + 64
+    print(f"[gpu] host region of {size} bytes", flush=True)
+    host = torch.empty(size, dtype=torch.uint8, pin_memory=True)
+    h = host.numpy()
+    for (_, _, n, llr), (lo, oo) in zip(frames, offs):
+        h[lo:lo + llr.nbytes] = llr.view(np.uint8)
+        h[oo:oo + (n + 7) // 8] = 0xAB
+    codes = [vit.make_code(k, g) for k, g in CODES]
+    srv = vit.Server(codes, host, tune=TUNE, llr_type=vit.VIT_LLR_I8, arena_bytes=1 << 20, max_frames=8,
+                     max_items=256)
+    try:
+        st, acc = srv.submit(requests(vit, host, frames, offs, list(range(len(frames)))))
+        assert st == vit.VIT_OK and acc == len(frames)
+        srv.drain(timeout_ms=30000)
+        comps = srv.poll()
+    finally:
+        srv.close()
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames))) and (comps["status"] == 0).all()
+    for t, fr in enumerate(frames):
+        oo = offs[t][1]
+        got = h[oo:oo + (fr[2] + 7) // 8]
+        np.testing.assert_array_equal(got, expected_oracle(fr, TUNE), err_msg=f"request at host offset {offs[t]}")
+    del host
+
+
 def test_late_short_frames_overtake_a_long_one(dev):
     torch, vit = dev
     rng = np.random.default_rng(5)
