@@ -249,6 +249,46 @@ def test_frames_beyond_4gib_offsets(dev):
     torch.cuda.empty_cache()
 
 
+def test_distinct_plans_on_threads(dev):
+    # distinct plans are safe to use from different threads at once: two
+    # threads, each with its own plan, stream, frames and buffers, decode
+    # repeatedly; every result equals the oracle's
+    import threading
+    torch, vit = dev
+    codes = [vit.make_code(*CODES[c]) for c in range(len(CODES))]
+    work = []
+    for seed in (51, 52):
+        rng = np.random.default_rng(seed)
+        frames, llr, out_bytes, _ = make_batch(rng, 80, [0, 1, 2, 3], 40, 3000, int8=seed == 52)
+        work.append((frames, llr, torch.from_numpy(llr).cuda(),
+                     [torch.zeros(out_bytes, dtype=torch.uint8, device="cuda") for _ in range(4)]))
+    torch.cuda.synchronize()
+    errors = []
+
+    def run(w):
+        frames, _, t_llr, outs = w
+        try:
+            stream = torch.cuda.Stream()
+            b = vit.Batch()
+            for out in outs:
+                b.decode(codes, frames, t_llr, out, tune=TUNE, stream=stream)
+            stream.synchronize()
+            b.close()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    print("[gpu] two threads, two plans", flush=True)
+    threads = [threading.Thread(target=run, args=(w,)) for w in work]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for frames, llr, _, outs in work:
+        for out in outs:
+            check_frames(out.cpu().numpy(), frames, llr, TUNE)
+
+
 def test_autotune_then_decode(dev):
     torch, vit = dev
     rng = np.random.default_rng(21)
