@@ -157,6 +157,33 @@ def test_full_frame_equals_bruteforce_integer_llrs_with_ties(k, gens, terminated
             assert float(met) == bfm
 
 
+@pytest.mark.parametrize("k,gens", [(3, (0o7, 0o5)), (7, (0o171, 0o133)), (7, (0o133, 0o171, 0o165)),
+                                    (9, (0o561, 0o753))])
+def test_full_frame_is_ml_over_all_2_16_messages(k, gens):
+    # terminated frames of n = 16 information bits: the full-frame decoder
+    # returns the message, among all 2^16, whose codeword (the independent
+    # numpy transmitter's) correlates best with the LLRs (eq. 2 summed over
+    # the frame: sum of llr * (1 - 2c)); every codeword is built from the 16
+    # impulse responses by GF(2) linearity of eq. 1
+    c = _code(k, gens)
+    rng = np.random.default_rng(216)
+    beta = len(gens)
+    n = 16
+    G = np.stack([synth.encode(k, gens, np.eye(n, dtype=np.uint8)[i], True) for i in range(n)]).astype(np.int64)
+    msgs = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.int64)  # bit i = message bit i
+    words = (msgs @ G) & 1                                                            # 2^16 codewords
+    sign = 1.0 - 2.0 * words
+    for trial in range(3):
+        bits = synth.info_bits(n, rng)
+        llr = synth.awgn_llr(synth.encode(k, gens, bits, True), 0.5, beta, rng).astype(np.float64)
+        metrics = sign @ llr
+        best = int(np.argmax(metrics))
+        assert np.sum(metrics == metrics[best]) == 1  # real-valued LLRs: no tie
+        out, met = vref.decode_full(c, llr, n, True, want_metric=True)
+        np.testing.assert_array_equal(out, msgs[best].astype(np.uint8), err_msg=f"trial {trial}")
+        assert met == pytest.approx(metrics[best], rel=1e-12, abs=1e-9)
+
+
 @pytest.mark.parametrize("k,gens", [(3, (0o7, 0o5)), (5, (0o23, 0o35)), (7, (0o171, 0o133)),
                                     (7, (0o133, 0o171, 0o165))])
 def test_full_frame_equals_bruteforce_real_llrs(k, gens):
