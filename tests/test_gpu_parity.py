@@ -241,6 +241,36 @@ def test_full_size_stream_k7(dev, L):
     _check(dev, k, gens, llr, n, L, 35)
 
 
+# ----------------------------------------------------------------------------- maximum likelihood, exhaustively
+
+@pytest.mark.parametrize("name", ["k3r12", "k7r12", "k7r13", "k9r12"])
+def test_full_frame_gpu_is_ml_over_all_2_16_messages(dev, name):
+    # the GPU's full-frame decode (L = 0) of a terminated 16-bit frame is the
+    # best of all 2^16 messages, scored with the independent numpy
+    # transmitter's codewords (no oracle involved); frames whose two best
+    # scores lie within 1e-3 are redrawn, so that fp32 rounding cannot decide
+    torch, vit = dev
+    k, gens = CODES[name]
+    beta = len(gens)
+    n = 16
+    G = np.stack([synth.encode(k, gens, np.eye(n, dtype=np.uint8)[i], True) for i in range(n)]).astype(np.int64)
+    msgs = ((np.arange(1 << n)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.int64)
+    sign = 1.0 - 2.0 * ((msgs @ G) & 1)
+    rng = np.random.default_rng(316)
+    done = 0
+    while done < 4:
+        bits = synth.info_bits(n, rng)
+        llr = synth.awgn_llr(synth.encode(k, gens, bits, True), 0.0, beta, rng)
+        metrics = sign @ llr.astype(np.float64)
+        top = np.sort(metrics)[-2:]
+        if top[1] - top[0] < 1e-3:
+            continue
+        want = synth.pack_bits(msgs[int(np.argmax(metrics))].astype(np.uint8))
+        got = _gpu(dev, k, gens, llr, n, 0, 0)
+        np.testing.assert_array_equal(got, want, err_msg=f"{name} frame {done}")
+        done += 1
+
+
 # ----------------------------------------------------------------------------- maximum size
 
 @pytest.mark.parametrize("kind", ["i8", "f32"])
