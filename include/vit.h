@@ -216,7 +216,10 @@ typedef struct {
 /* A plan owns pinned host staging for work lists, a captured hipGraph that is
  * reused while the buffers and shapes stay the same, and the autotuner's
  * choices.  It never allocates device memory: the caller supplies the
- * workspace.  A plan is not thread-safe; distinct plans are independent. */
+ * workspace.  A plan is not thread-safe, and the batch entry points are to be
+ * called from one thread at a time: two threads decoding with two plans at
+ * once ended the process once (a host-side crash inside vit_decode_batch
+ * whose cause is not known). */
 typedef struct vit_plan vit_plan;
 
 int vit_plan_create(vit_plan **plan);
