@@ -273,7 +273,7 @@ def test_full_frame_gpu_is_ml_over_all_2_16_messages(dev, name):
 
 # ----------------------------------------------------------------------------- maximum size
 
-@pytest.mark.parametrize("kind", ["i8", "f32"])
+@pytest.mark.parametrize("kind", ["i8", "i8m16", "f32"])
 def test_maximum_stream_size_sampled(dev, kind):
     # a K=7 r1/2 stream just under the library's limits (2^32 LLR bytes and
     # 2^31 stages), where the kernels' 32-bit byte offsets are at their
@@ -286,18 +286,19 @@ def test_maximum_stream_size_sampled(dev, kind):
     ocode = vref.make_code(k, list(gens))
     L, v = 512, 35
     v1, v2 = v // 2, v - v // 2
-    elem = 1 if kind == "i8" else 4
+    elem = 4 if kind == "f32" else 1
     N = ((1 << 32) - 64) // (2 * elem)
     N = min(N, (1 << 31) - 64)
     n = N - (k - 1)
     print(f"[gpu] maximum size {kind}: n={n} N={N} LLR bytes={2 * N * elem}", flush=True)
     g = torch.Generator(device="cuda")
     g.manual_seed(2024)
-    if kind == "i8":
+    if kind != "f32":
         llr = torch.randint(-127, 128, (2 * N,), dtype=torch.int8, device="cuda", generator=g)
     else:
         llr = torch.randint(-40, 41, (2 * N,), dtype=torch.int32, device="cuda", generator=g).to(torch.float32)
-    out = vit.decode(code, llr, n, L, v)
+    # i8m16: the 16-bit modulo-metric kernels (two blocks per wave)
+    out = vit.decode(code, llr, n, L, v, metric_bits=16 if kind == "i8m16" else 0)
     torch.cuda.synchronize()
     nblocks = -(-n // L)
     rng = np.random.default_rng(5)
