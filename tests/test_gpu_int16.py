@@ -93,6 +93,22 @@ def test_int16_geometry_sweep(dev, name, n, L, v, v1, terminated):
     _check(dev, k, gens, q, n, L, v, v1, terminated)
 
 
+@pytest.mark.parametrize("terminated", [True, False])
+@pytest.mark.parametrize("name", list(CODES))
+def test_int16_edge_lengths_per_code(dev, name, terminated):
+    # lengths at this code's own edges and at the block edges, overlaps 0, 1,
+    # odd and 5k, the overlap split at both extremes and at the default; one
+    # to three blocks, so a wave pairs a block with an empty partner or with
+    # the ragged last one
+    k, gens = CODES[name]
+    L = 16
+    for n in sorted({1, k - 1, k, k + 1, L - 1, L, L + 1, 2 * L + 1}):
+        q = _qawgn(k, gens, n, 1.0, seed=2000 * k + 10 * n + terminated, terminated=terminated)
+        for v in (0, 1, 2 * k + 1, 5 * k):
+            for v1 in sorted({None, 0, v}, key=lambda x: -1 if x is None else x):
+                _check(dev, k, gens, q, n, L, v, v1, terminated)
+
+
 @pytest.mark.parametrize("name", list(CODES))
 def test_int16_full_range_int8_and_ties(dev, name):
     # uniform int8 over the whole range (-128 included), and integer LLRs in

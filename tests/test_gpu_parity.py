@@ -114,6 +114,21 @@ def test_geometry_sweep_awgn(dev, name, n, L, v, v1, terminated):
     _check(dev, k, gens, llr, n, L, v, v1, terminated)
 
 
+@pytest.mark.parametrize("terminated", [True, False])
+@pytest.mark.parametrize("name", list(CODES))
+def test_edge_lengths_per_code(dev, name, terminated):
+    # lengths at this code's own edges (1, k-1, k, k+1) and at the block
+    # edges (L-1, L, L+1, 2L+1), overlaps 0, 1, odd and 5k, with the
+    # overlap split at both extremes as well as the default
+    k, gens = CODES[name]
+    L = 16
+    for n in sorted({1, k - 1, k, k + 1, L - 1, L, L + 1, 2 * L + 1}):
+        llr = _awgn(k, gens, n, 1.0, seed=1000 * k + 10 * n + terminated, terminated=terminated)
+        for v in (0, 1, 2 * k + 1, 5 * k):
+            for v1 in sorted({None, 0, v}, key=lambda x: -1 if x is None else x):
+                _check(dev, k, gens, llr, n, L, v, v1, terminated)
+
+
 # ----------------------------------------------------------------------------- ties and special values
 
 @pytest.mark.parametrize("name", list(CODES))
