@@ -238,6 +238,53 @@ def test_blocked_equals_bruteforce_per_window(k, gens, terminated):
             np.testing.assert_array_equal(got, want, err_msg=f"n={n} L={L} v1={v1} v2={v2} {dt}")
 
 
+@pytest.mark.parametrize("k,gens", [(3, (0o7, 0o5)), (4, (0o17, 0o13)), (5, (0o23, 0o35)),
+                                    (4, (0o13, 0o15, 0o17, 0o11))])
+def test_window_is_ml_over_every_path_of_the_window(k, gens):
+    # One window of the blocked decoder (Sec. III) is the best path over the
+    # window's stages: from state 0 when the start is known, else from any
+    # state at no cost; into state 0 when the end is fixed, else into any
+    # state.  Every candidate path is enumerated here as k-1 history bits (the
+    # start state) followed by the window's inputs and encoded by the
+    # independent numpy transmitter (by GF(2) linearity of eq. 1), the history
+    # stages' outputs dropped; its score is eq. 2 summed over the window.
+    c = _code(k, gens)
+    beta = len(gens)
+    P = k - 1
+    rng = np.random.default_rng(300 + 10 * k + beta)
+    N = 40
+    ties = 0
+    for trial in range(12):
+        W = int(rng.integers(1, 19 - P))
+        s = int(rng.integers(0, N - W + 1))
+        e = s + W
+        start_known, end_zero = bool(trial & 1), bool(trial & 2) and W > P
+        lo = int(rng.integers(s, e))
+        hi = int(rng.integers(lo + 1, e + 1))
+        llr = rng.normal(0.0, 2.0, N * beta)
+        nin = P + W
+        G = np.stack([synth.encode(k, gens, np.eye(nin, dtype=np.uint8)[i], False)
+                      for i in range(nin)]).astype(np.int64)[:, P * beta:]
+        seqs = ((np.arange(1 << nin)[:, None] >> np.arange(nin)[None, :]) & 1).astype(np.int64)
+        keep = np.ones(len(seqs), dtype=bool)
+        if start_known:
+            keep &= ~seqs[:, :P].any(axis=1)
+        if end_zero:
+            keep &= ~seqs[:, nin - P:].any(axis=1)
+        seqs = seqs[keep]
+        metrics = (1.0 - 2.0 * ((seqs @ G) & 1)) @ llr[s * beta:e * beta]
+        top = metrics.max()
+        # paths with the same outputs tie exactly (a free start in a window
+        # shorter than the register); any of the best is then a valid answer
+        best = seqs[metrics == top][:, P + lo - s:P + hi - s].astype(np.uint8)
+        got, met = vref.window_f64(c, llr, s, e, start_known, end_zero, lo, hi)
+        what = f"s={s} e={e} known={start_known} end0={end_zero} emit=[{lo},{hi})"
+        assert (best == got[None, :]).all(axis=1).any(), f"{what}: {got} not among {best}"
+        assert met == pytest.approx(top, rel=1e-12, abs=1e-9), what
+        ties += len(best) > 1
+    assert ties < 12
+
+
 def _longest_zero_output_run(k, gens):
     """Longest run of zero-output trellis branches that starts in a nonzero state
     (a graph search on the encoder FSM, independent of any decoder)."""
