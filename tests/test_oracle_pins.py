@@ -282,6 +282,21 @@ def test_window_is_ml_over_every_path_of_the_window(k, gens):
         assert (best == got[None, :]).all(axis=1).any(), f"{what}: {got} not among {best}"
         assert met == pytest.approx(top, rel=1e-12, abs=1e-9), what
         ties += len(best) > 1
+        # the oracle's own exhaustive search (the reference of other pins)
+        # against the same enumeration: the whole window's bits, free or
+        # fixed end state (state = last k-1 inputs, newest in the top bit)
+        whole = seqs[metrics == top][:, P:].astype(np.uint8)
+        bf, bfm = vref.bruteforce_window(c, llr, s, e, start_known, end_zero)
+        assert (whole == bf[None, :]).all(axis=1).any() and bfm == pytest.approx(top, rel=1e-12, abs=1e-9), what
+        endst = sum(seqs[:, nin - 1 - m] << (P - 1 - m) for m in range(P))
+        j = int(rng.integers(0, 1 << P))
+        mj = np.where(endst == j, metrics, -np.inf)
+        if np.isfinite(mj).any():
+            topj = mj.max()
+            bfj, bfjm = vref.bruteforce_window_to(c, llr, s, e, start_known, j)
+            wj = seqs[mj == topj][:, P:].astype(np.uint8)
+            assert (wj == bfj[None, :]).all(axis=1).any() and bfjm == pytest.approx(topj, rel=1e-12, abs=1e-9), \
+                f"{what} end state {j}"
     assert ties < 12
 
 
