@@ -752,7 +752,7 @@ def main():
         "bound": "alu",
         "achieved": round(head["tops"], 3),
         "peak": ALU_PEAK_TOPS,
-        "unit": "T op/s",
+        "unit": "TFLOP/s",  # fp32 adds, compares and selects, one flop each
         "frac": round(head["tops"] / ALU_PEAK_TOPS, 4),
         "mix_peak": round(MIX_PEAK_TOPS, 2),
         "mix_frac": round(head["tops"] / MIX_PEAK_TOPS, 4),
