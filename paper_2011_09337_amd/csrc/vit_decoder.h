@@ -447,6 +447,21 @@ struct Decoder {
     }
   }
 
+  // The value of lane ^ m for m = 1, 2, 7, 8, 16, 32 (Q = 0..5): DPP moves
+  // within rows (quad_perm, row_half_mirror, row_ror:8) and in-place
+  // v_permlane16_swap / v_permlane32_swap of a copy.
+  template <int Q>
+  __device__ __forceinline__ static float lane_xor(float v) {
+    int i = __builtin_bit_cast(int, v);
+    if constexpr (Q == 0) i = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
+    else if constexpr (Q == 1) i = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    else if constexpr (Q == 2) i = __builtin_amdgcn_mov_dpp(i, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if constexpr (Q == 3) i = __builtin_amdgcn_mov_dpp(i, 0x128, 0xF, 0xF, false);  // row_ror:8
+    else if constexpr (Q == 4) asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %0" : "+v"(i));
+    else asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %0" : "+v"(i));
+    return __builtin_bit_cast(float, i);
+  }
+
   // Rotation of a P-bit slot or state index by r places (0 <= r < P).
   __device__ __forceinline__ static uint32_t rotr_p(uint32_t x, int r) {
     return ((x >> r) | (x << ((P - r) % P))) & (uint32_t)(S - 1);
@@ -474,12 +489,43 @@ struct Decoder {
       sigs[reg] = ((slot >> qg) & 1) ? -o[reg] : o[reg];
       best = __builtin_fmaxf(best, sigs[reg]);
     }
-    // (lane exchanges by ds_bpermute at lane ^ m; the compiler's shuffle
-    // helper adds a width compare that does not compile here)
+    if constexpr (S >= 64) {
+      // Every lane holds distinct slots: the largest metric by a butterfly of
+      // in-register lane exchanges (xor 1, 2, 7, 8, 16, 32; no LDS round
+      // trips), then, when a single slot holds it (the usual case with
+      // real-valued LLRs), that slot straight from the ballot.
+      best = __builtin_fmaxf(best, lane_xor<0>(best));
+      best = __builtin_fmaxf(best, lane_xor<1>(best));
+      best = __builtin_fmaxf(best, lane_xor<2>(best));
+      best = __builtin_fmaxf(best, lane_xor<3>(best));
+      best = __builtin_fmaxf(best, lane_xor<4>(best));
+      best = __builtin_fmaxf(best, lane_xor<5>(best));
+      uint64_t hit[REGS];
+      int nhit = 0;
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1)
-      best = __builtin_fmaxf(best, __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
-                                                                  (lane ^ m) << 2, __builtin_bit_cast(int, best))));
+      for (int reg = 0; reg < REGS; ++reg) {
+        hit[reg] = __builtin_amdgcn_ballot_w64(sigs[reg] == best);
+        nhit += __builtin_popcountll(hit[reg]);
+      }
+      if (nhit == 1) {
+        int slot = 0;
+#pragma unroll
+        for (int reg = 0; reg < REGS; ++reg)
+          if (hit[reg]) {
+            const int l = __builtin_ctzll(hit[reg]);
+            slot = (reg << 6) | (l ^ (((l >> 2) & 1) ? 3 : 0));
+          }
+        return slot & (S - 1);
+      }
+    } else {
+      // (lane exchanges by ds_bpermute at lane ^ m; the compiler's shuffle
+      // helper adds a width compare that does not compile here)
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1)
+        best = __builtin_fmaxf(best, __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                                    (lane ^ m) << 2, __builtin_bit_cast(int, best))));
+    }
+    // ties (or fewer states than lanes): the lowest label holding the maximum
     int lab = 0x7fffffff;
 #pragma unroll
     for (int reg = 0; reg < REGS; ++reg) {
