@@ -476,9 +476,8 @@ struct Decoder {
   template <int G>
   __device__ __forceinline__ int best_slot_after() const {
     constexpr int qg = G % P, rot = (G + 1) % P;
-    // Two reductions without branches (this runs between trellis steps, with
-    // their pending compare masks live in SGPRs): the largest metric by max,
-    // then the lowest label among the slots holding it by min.
+    // The largest metric by max, then the slot holding it; this runs between
+    // trellis steps, with their pending compare masks live in SGPRs.
     float best = -INFINITY;
     int labs[REGS];
     float sigs[REGS];
