@@ -200,6 +200,62 @@ def test_requests_beyond_4gib_in_the_host_region(dev):
     del host
 
 
+# codes beside the benchmark's three: K=3, a K=5 code without the newest-input
+# tap, K=8 (two registers of states per lane) and K=4 at rate 1/4
+EDGE_CODES = [(3, (0o7, 0o5)), (5, (0o22, 0o35)), (8, (0o247, 0o371)), (4, (0o13, 0o15, 0o17, 0o11))]
+EDGE_TUNE = [(16, 15, -1, 1), (16, 0, -1, 1), (32, 40, 0, 2), (16, 7, 7, 1)]
+
+
+@pytest.mark.parametrize("int8", [False, True])
+def test_edge_lengths_and_other_codes(dev, int8):
+    # every frame length at its code's own edges (1, 2, k-1, k, k+1) and at
+    # the block edges (L-1, L, L+1, 2L+1), terminated and open, through the
+    # scheduler with a small arena and few slots and items (so frames wait
+    # for memory and span iterations); each result equals the oracle's
+    torch, vit = dev
+    rng = np.random.default_rng(31 + int(int8))
+    frames = []
+    for cid, (k, gens) in enumerate(EDGE_CODES):
+        L = EDGE_TUNE[cid][0]
+        for n in sorted({1, 2, k - 1, k, k + 1, L - 1, L, L + 1, 2 * L + 1}):
+            for term in (1, 0):
+                e = float(rng.uniform(0.5, 4.0))
+                llr = synth.awgn_llr(synth.encode(k, gens, synth.info_bits(n, rng), bool(term)), e, len(gens), rng)
+                if int8:
+                    llr = vref.quantize_i8(llr, 8.0 * synth.noise_sigma(e, len(gens)) ** 2 / 2.0)
+                frames.append((cid, term, n, llr))
+    host, offs = place(torch, frames, rng)
+    codes = [vit.make_code(k, g) for k, g in EDGE_CODES]
+    srv = vit.Server(codes, host, tune=EDGE_TUNE, llr_type=vit.VIT_LLR_I8 if int8 else vit.VIT_LLR_F32,
+                     arena_bytes=16 << 10, max_frames=6, max_items=20)
+    before = host.numpy().copy()
+    try:
+        order = rng.permutation(len(frames))
+        for wave in np.array_split(order, 4):
+            st, acc = srv.submit(requests(vit, host, frames, offs, [int(t) for t in wave]))
+            assert st == vit.VIT_OK and acc == len(wave)
+        srv.drain(timeout_ms=60000)
+        comps = srv.poll()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert sorted(comps["tag"].tolist()) == list(range(len(frames)))
+    assert (comps["status"] == 0).all()
+    assert stats["completed"] == len(frames) and stats["iterations"] > 1
+    h = host.numpy()
+    outside = np.ones(h.size, dtype=bool)
+    for t, fr in enumerate(frames):
+        outside[offs[t][1]:offs[t][1] + (fr[2] + 7) // 8] = False
+    np.testing.assert_array_equal(h[outside], before[outside], err_msg="bytes outside the outputs changed")
+    for t, (cid, term, n, llr) in enumerate(frames):
+        k, gens = EDGE_CODES[cid]
+        L, v, v1, _ = EDGE_TUNE[cid]
+        v1 = v // 2 if v1 < 0 else v1
+        want = synth.pack_bits(vref.decode_blocked(vref.make_code(k, list(gens)), llr, n, L, v1, v - v1, bool(term)))
+        oo = offs[t][1]
+        np.testing.assert_array_equal(h[oo:oo + want.size], want, err_msg=f"code {cid} n={n} term={term}")
+
+
 def test_late_short_frames_overtake_a_long_one(dev):
     torch, vit = dev
     rng = np.random.default_rng(5)
