@@ -447,19 +447,35 @@ struct Decoder {
     }
   }
 
-  // The value of lane ^ m for m = 1, 2, 7, 8, 16, 32 (Q = 0..5): DPP moves
-  // within rows (quad_perm, row_half_mirror, row_ror:8) and in-place
-  // v_permlane16_swap / v_permlane32_swap of a copy.
-  template <int Q>
-  __device__ __forceinline__ static float lane_xor(float v) {
-    int i = __builtin_bit_cast(int, v);
-    if constexpr (Q == 0) i = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
-    else if constexpr (Q == 1) i = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    else if constexpr (Q == 2) i = __builtin_amdgcn_mov_dpp(i, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    else if constexpr (Q == 3) i = __builtin_amdgcn_mov_dpp(i, 0x128, 0xF, 0xF, false);  // row_ror:8
-    else if constexpr (Q == 4) asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %0" : "+v"(i));
-    else asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %0" : "+v"(i));
-    return __builtin_bit_cast(float, i);
+  // Wave-wide max of v, in every lane: a butterfly over lane xor 1, 2, 7, 8
+  // (max fused with a DPP read: quad_perm, row_half_mirror, row_ror:8) and
+  // xor 16, 32 (in-place v_permlane16/32_swap of a copy).  For the finite
+  // metrics here it equals a chain of fmaxf without the compiler's NaN
+  // quieting of every operand.  Each s_nop 1 covers the two wait states
+  // between a VALU write and the next DPP or permlane read of that register.
+  __device__ __forceinline__ static float wave_max(float v) {
+    float t;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_max_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_f32_dpp %0, %0, %0 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32 %1, %0\n\t"
+        "s_nop 1\n\t"
+        "v_permlane16_swap_b32 %1, %1\n\t"
+        "s_nop 1\n\t"
+        "v_max_f32 %0, %0, %1\n\t"
+        "v_mov_b32 %1, %0\n\t"
+        "s_nop 1\n\t"
+        "v_permlane32_swap_b32 %1, %1\n\t"
+        "s_nop 1\n\t"
+        "v_max_f32 %0, %0, %1"
+        : "+v"(v), "=&v"(t));
+    return v;
   }
 
   // Rotation of a P-bit slot or state index by r places (0 <= r < P).
@@ -486,19 +502,16 @@ struct Decoder {
       const int slot = ((reg << 6) | slot0) & (S - 1);
       labs[reg] = (int)rotr_p((uint32_t)slot, rot);
       sigs[reg] = ((slot >> qg) & 1) ? -o[reg] : o[reg];
-      best = __builtin_fmaxf(best, sigs[reg]);
     }
     if constexpr (S >= 64) {
       // Every lane holds distinct slots: the largest metric by a butterfly of
-      // in-register lane exchanges (xor 1, 2, 7, 8, 16, 32; no LDS round
-      // trips), then, when a single slot holds it (the usual case with
-      // real-valued LLRs), that slot straight from the ballot.
-      best = __builtin_fmaxf(best, lane_xor<0>(best));
-      best = __builtin_fmaxf(best, lane_xor<1>(best));
-      best = __builtin_fmaxf(best, lane_xor<2>(best));
-      best = __builtin_fmaxf(best, lane_xor<3>(best));
-      best = __builtin_fmaxf(best, lane_xor<4>(best));
-      best = __builtin_fmaxf(best, lane_xor<5>(best));
+      // in-register lane exchanges (no LDS round trips), then, when a single
+      // slot holds it (the usual case with real-valued LLRs), that slot
+      // straight from the ballot.
+      float m = sigs[0];
+#pragma unroll
+      for (int reg = 1; reg < REGS; ++reg) m = __builtin_fmaxf(m, sigs[reg]);
+      best = wave_max(m);
       uint64_t hit[REGS];
       int nhit = 0;
 #pragma unroll
@@ -517,6 +530,8 @@ struct Decoder {
         return slot & (S - 1);
       }
     } else {
+#pragma unroll
+      for (int reg = 0; reg < REGS; ++reg) best = __builtin_fmaxf(best, sigs[reg]);
       // (lane exchanges by ds_bpermute at lane ^ m; the compiler's shuffle
       // helper adds a width compare that does not compile here)
 #pragma unroll
