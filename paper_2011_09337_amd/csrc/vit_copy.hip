@@ -1,8 +1,9 @@
-// vit_copy.hip -- gather/scatter of byte ranges, used by the serving loop to
-// move its work list and the LLRs of newly admitted frames from pinned host
-// memory into the device, and decoded bytes back, in one launch per
-// iteration however many frames it holds.  The range list itself may sit in
-// device memory or in mapped pinned host memory.
+// vit_copy.hip -- copies of a list of byte ranges, used by the serving loop
+// to move its work list and the LLRs of newly admitted frames from pinned
+// host memory into the device in one launch per iteration, however many
+// frames it holds (the decode kernels write the decoded bytes back into the
+// host region themselves).  The range list itself may sit in device memory or
+// in mapped pinned host memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
