@@ -280,6 +280,19 @@ struct Decoder {
     return (c ^ (up ? NCODE - 1 : 0)) << 2;
   }
 
+  // Codes whose generators all tap both ends of the register: the partner
+  // address above reduces to the complemented output pattern of the rotated
+  // slot index, and bit b of that pattern is the parity of the slot index
+  // with generator b's low P bits rotated left by q (uniform, so the rotation
+  // is scalar work).
+  __device__ __forceinline__ int partner_addr_std(const uint32_t *gen, int q, int reg) const {
+    const uint32_t st = (uint32_t)(((reg << 6) | slot0) & (S - 1));
+    int c = 0;
+#pragma unroll
+    for (int b = 0; b < BETA; ++b) c |= parity32(rotl_p(gen[b] & (uint32_t)(S - 1), q) & st) << b;
+    return (c ^ (NCODE - 1)) << 2;
+  }
+
   __device__ __forceinline__ void setup(const uint32_t *gen) {
     lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     slot0 = lane ^ (((lane >> 2) & 1) ? 3 : 0);  // inverse of the lane_vec map
@@ -291,8 +304,12 @@ struct Decoder {
     for (int q = 0; q < P; ++q) {
 #pragma unroll
       for (int reg = 0; reg < REGS; ++reg) {
-        addr_x[q][reg] = metric_addr(gen, q, reg, false);
-        if constexpr (!STD) addr_y[q][reg] = metric_addr(gen, q, reg, true);
+        if constexpr (STD) {
+          addr_x[q][reg] = partner_addr_std(gen, q, reg);
+        } else {
+          addr_x[q][reg] = metric_addr(gen, q, reg, false);
+          addr_y[q][reg] = metric_addr(gen, q, reg, true);
+        }
       }
       const int st0 = slot0 & (S - 1);
       const int bq = (st0 >> q) & 1, bqm = (st0 >> ((q + P - 1) % P)) & 1;
@@ -556,32 +573,9 @@ struct Decoder {
 
   // Slot index of the best state at a body end, where slot j holds state j
   // with the sign convention of the body's last phase; lowest index on ties.
-  // Uniform across the wave.
-  __device__ __forceinline__ int best_state() const {
-    constexpr int qlast = (BODY - 1) % P;
-    float best = -INFINITY;
-    int lab = 0x7fffffff;
-#pragma unroll
-    for (int reg = 0; reg < REGS; ++reg) {
-      const int slot = (reg << 6) | slot0;
-      const int label = slot & (S - 1);
-      const float sig = ((slot >> qlast) & 1) ? -o[reg] : o[reg];
-      if (reg == 0 || sig > best) {
-        best = sig;
-        lab = label;
-      }
-    }
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      const float ob = __shfl_xor(best, m);
-      const int ol = __shfl_xor(lab, m);
-      if (ob > best || (ob == best && ol < lab)) {
-        best = ob;
-        lab = ol;
-      }
-    }
-    return __builtin_amdgcn_readfirstlane(lab);
-  }
+  // Uniform across the wave.  This is the snapshot after the body's last step
+  // (BODY is a multiple of P, so the rotation there is the identity).
+  __device__ __forceinline__ int best_state() const { return best_slot_after<BODY - 1>(); }
 
   // Traceback (Algorithm 2) through one group (body) of survivor words for
   // each of NCH independent chains, interleaved so that the scalar steps of
